@@ -1,0 +1,207 @@
+/*
+ * ccd.h - C ABI of the MI355X (gfx950) inclusion-based continuous collision
+ * detection library.
+ *
+ * The library decides, for each vertex-face (VF) or edge-edge (EE) pair whose
+ * vertices move linearly over t in [0, 1], whether and when the pair touches,
+ * with the root finder of Wang, Ferguson, Schneider, Jiang, Attene and Panozzo,
+ * "A Large Scale Benchmark and an Inclusion-Based Algorithm for Continuous
+ * Collision Detection" (ACM TOG 40(5), 2021):
+ *
+ *   - the problem is a root of F_vf or F_ee on Omega (Sec. 3, eqs. F-vf, F-ee);
+ *   - a box I of the (t, u, v) domain is tested with the axis-aligned box of F
+ *     at the 8 corners of I (Sec. 4.2, eq. box) against the floating-point
+ *     filter eps_c = K gamma_c^3 (Sec. 4.2, eq. ccd-error);
+ *   - boxes are bisected breadth first, level by level, along the axis with
+ *     the largest estimated co-domain extent (Alg. 2, SPLIT; eq. kappas) until
+ *     the first colliding box of a level is smaller than delta or inside the
+ *     filter cube, or until m_I boxes have been checked (Alg. 2);
+ *   - with a minimum separation d > 0 the box is enlarged by d and the filter
+ *     constants change (Sec. 5.1, eq. msccd-error); distances are L-infinity.
+ *
+ * All arithmetic is IEEE binary64 with no contraction; results are bit-for-bit
+ * reproducible and independent of batch composition, launch shape and tuning.
+ *
+ * Conventions
+ *   - Functions return CCD_OK (0) or a negative CCD_E* code; nothing throws.
+ *   - Query coordinates: 8 points x 3 coordinates.  Points 0..3 are at t = 0,
+ *     points 4..7 are the same vertices at t = 1.  VF: p, v1, v2, v3.
+ *     EE: p1, p2 (edge A) and p3, p4 (edge B).
+ *   - A query is invalid if a coordinate is not finite or exceeds 1e300 in
+ *     magnitude, delta is not a positive finite number, max_iter < 1, min_sep is
+ *     negative or not finite, min_sep is not below min_c gamma_c (Sec. 5.1
+ *     assumes d < gamma), or t_max != 1.
+ *   - Output convention (Alg. 2): hit = (toi <= 1); no collision is
+ *     toi = +inf, t_width = 0.  toi is a conservative (never late) estimate of
+ *     the earliest contact time; t_width is w(I_t) of the level it came from.
+ */
+#ifndef CCD_H
+#define CCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define CCD_OK 0
+#define CCD_EINVAL (-1)     /* invalid argument or query; outputs untouched */
+#define CCD_ENOMEM (-2)     /* device memory budget too small for the request */
+#define CCD_EDEVICE (-3)    /* HIP runtime error or missing gfx950 device */
+#define CCD_EAGAIN (-4)     /* serving: request does not fit right now */
+#define CCD_ETIMEDOUT (-5)  /* serving: wait timed out */
+#define CCD_ECANCELED (-6)  /* serving: request cancelled / server closed */
+
+/* Query kinds. */
+#define CCD_KIND_VF 0
+#define CCD_KIND_EE 1
+
+/* Per-query status bits. */
+#define CCD_ST_CAP 0x01     /* returned because m_I checks were reached (Alg. 2) */
+#define CCD_ST_CARRY 0x02   /* returned a remembered terminal box (see CCD_FLAG_LITERAL) */
+#define CCD_ST_DEPTH 0x04   /* returned box was terminal only because a split would
+                               go below 2^-52 on its axis */
+#define CCD_ST_INVALID 0x80 /* device-side validation rejected the query
+                               (toi = t_width = NaN, hit = 0, n_checks = 0) */
+
+/* Parameter flags. */
+#define CCD_FLAG_LITERAL 0x1u /* drop, as Alg. 2 is printed, a colliding box that meets
+                                 the termination test but is not the first colliding box
+                                 of its level.  Default (flag clear): remember the
+                                 earliest such box and return it once no earlier
+                                 candidate is left, which keeps toi conservative when
+                                 the first box's region later turns out empty. */
+
+/* Parameters of one query (Alg. 2 inputs; Sec. 5.1 adds min_sep). */
+typedef struct ccd_params {
+    double delta;      /* tolerance delta > 0 on the co-domain width; paper default 1e-6 */
+    int64_t max_iter;  /* m_I >= 1: maximum number of box checks; paper default 1e6 */
+    double min_sep;    /* d >= 0: minimum separation, L-infinity; 0 = standard CCD */
+    double t_max;      /* must be 1.0 (reserved for a shortened time interval) */
+    uint32_t flags;    /* CCD_FLAG_* */
+    uint32_t reserved; /* must be 0 */
+} ccd_params;
+
+/* Result of one query. */
+typedef struct ccd_result {
+    double toi;        /* earliest conservative time of impact, +inf if none */
+    double t_width;    /* w(I_t) of the returned level, 0 if none */
+    uint64_t n_checks; /* box checks of the sequential Alg. 2, saturated at m_I */
+    uint8_t hit;       /* toi <= 1 */
+    uint8_t status;    /* CCD_ST_* bits */
+    uint8_t reserved[6];
+} ccd_result;
+
+/*
+ * Single queries on the GPU of a library-owned default context (device 0),
+ * run through the same kernels as ccd_batch.  x0: the 4 points at t = 0, x1:
+ * the same points at t = 1 (host memory).  Blocking.  Returns CCD_EINVAL for
+ * an invalid query or NULL pointer (out untouched), CCD_EDEVICE without a GPU.
+ */
+int ccd_vf(const double x0[4][3], const double x1[4][3], const ccd_params* params,
+           ccd_result* out);
+int ccd_ee(const double x0[4][3], const double x1[4][3], const ccd_params* params,
+           ccd_result* out);
+
+/* Fills *p with the paper's defaults: delta 1e-6, max_iter 1e6, min_sep 0, t_max 1. */
+void ccd_params_default(ccd_params* p);
+
+/* ------------------------------------------------------------------------- */
+/* Contexts and batches. */
+
+typedef struct ccd_context ccd_context;
+
+/*
+ * Creates a context on HIP device `device` whose scratch allocations (frontier
+ * arenas, promotion records, queues) stay within mem_budget_bytes of device
+ * memory (0 selects a default of 16 GiB).  The context owns its scratch; it is
+ * not thread-safe (one host thread at a time per context).
+ */
+int ccd_context_create(int device, size_t mem_budget_bytes, ccd_context** out);
+void ccd_context_destroy(ccd_context* ctx);
+
+/* Engines selectable with ccd_context_set_engine. */
+#define CCD_ENGINE_PERSISTENT 0 /* persistent kernels: lane per light query, group per
+                                   wide query, block per huge query (default) */
+#define CCD_ENGINE_PLAIN 1      /* one thread per query, same fallback tiers */
+int ccd_context_set_engine(ccd_context* ctx, int engine);
+
+/* Launch and capacity knobs (what the autotuner searches); 0 keeps a field's
+ * current value.  Values are clamped to supported ranges. */
+typedef struct ccd_tuning {
+    int32_t lane_waves_per_cu;    /* resident waves per CU of the lane-per-query kernel */
+    int32_t lane_capacity;        /* boxes per level a lane may hold (8..256) */
+    int64_t lane_budget;          /* checks a lane spends before it hands the query on */
+    int32_t group_waves;          /* waves per group working on one wide query (1, 2, 4, 8) */
+    int32_t group_count;          /* resident groups of the wide-query kernel */
+    int64_t group_capacity;       /* boxes per level of a group's arena */
+    int32_t block_count;          /* resident blocks of the huge-query kernel */
+    int32_t reserved;
+} ccd_tuning;
+int ccd_context_get_tuning(ccd_context* ctx, ccd_tuning* out);
+int ccd_context_set_tuning(ccd_context* ctx, const ccd_tuning* t);
+
+/* A batch of n queries in structure-of-arrays layout. */
+typedef struct ccd_batch_desc {
+    int64_t n;                 /* number of queries, >= 0 */
+    const double* pos;         /* [24][n]: pos[(3k+c)*n + q] = coordinate c of point k */
+    const uint8_t* kind;       /* [n] CCD_KIND_*; NULL: every query is default_kind */
+    uint8_t default_kind;
+    uint8_t reserved[7];
+    const double* delta_q;     /* [n] per-query delta or NULL (params.delta) */
+    const int64_t* max_iter_q; /* [n] per-query m_I or NULL (params.max_iter) */
+    const double* min_sep_q;   /* [n] per-query d or NULL (params.min_sep) */
+    ccd_params params;         /* batch parameters (flags and t_max always from here) */
+    int32_t on_device;         /* 1: all pointers (inputs and outputs) are device memory */
+    int32_t reserved2;
+} ccd_batch_desc;
+
+/* Outputs of a batch, one entry per query (caller-owned). */
+typedef struct ccd_result_soa {
+    double* toi;
+    double* t_width;
+    uint8_t* hit;
+    uint64_t* n_checks;
+    uint8_t* status;
+} ccd_result_soa;
+
+/*
+ * Solves a batch.  `stream` is a hipStream_t (NULL: the legacy default stream).
+ *   on_device = 1: inputs and outputs are device pointers; the call is
+ *     asynchronous and completes on `stream`; inputs are validated on the
+ *     device and invalid queries get status CCD_ST_INVALID.  Buffers must stay
+ *     alive until the stream has passed the call.
+ *   on_device = 0: host pointers; the whole batch is validated on the host
+ *     first (CCD_EINVAL, outputs untouched, if any query is invalid), then
+ *     copied, solved and copied back; the call returns when results are in the
+ *     host arrays.
+ * Results do not depend on batch composition, engine or tuning.  The context's
+ * scratch is reused by the next call on it: calls on one context must not
+ * overlap on different streams.
+ */
+int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa* out,
+              void* stream);
+
+/* Counters of the last ccd_batch on a context (host copy; synchronises). */
+typedef struct ccd_stats {
+    uint64_t checks[3][2];   /* box checks executed by tier [lane, group, block] x kind [VF, EE] */
+    uint64_t promoted[2];    /* queries handed to the group tier, to the block tier */
+    float kernel_ms[4];      /* device time of [partition, lane, group, block] kernels
+                                (only when timing is enabled, else 0) */
+} ccd_stats;
+int ccd_context_enable_timing(ccd_context* ctx, int enable);
+int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
+
+/* Message for a return code. */
+const char* ccd_strerror(int code);
+
+/* Text of the last HIP failure or capacity error seen by the library on the
+ * calling thread ("" if none); valid until the next library call. */
+const char* ccd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCD_H */

@@ -1,0 +1,302 @@
+"""Python binding of the C ABI in include/ccd.h (argument marshalling only).
+
+Every step of the root finder runs in the HIP library ``libccd.so`` next to
+this file; PyTorch is used only for device memory and streams.  Importing this
+module does not touch the GPU; the library is loaded on first use and a missing
+library raises an error (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+KIND_VF, KIND_EE = 0, 1
+ST_CAP, ST_CARRY, ST_DEPTH, ST_INVALID = 0x01, 0x02, 0x04, 0x80
+FLAG_LITERAL = 0x1
+ENGINE_PERSISTENT, ENGINE_PLAIN = 0, 1
+
+EXPORTED = [
+    "ccd_vf", "ccd_ee", "ccd_params_default", "ccd_context_create", "ccd_context_destroy",
+    "ccd_context_set_engine", "ccd_context_get_tuning", "ccd_context_set_tuning", "ccd_batch",
+    "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
+]
+
+
+class CCDError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _lib().ccd_strerror(code).decode() if _LIB is not None else str(code)
+        detail = _lib().ccd_last_error().decode() if _LIB is not None else ""
+        if detail:
+            msg = f"{msg} [{detail}]"
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("max_iter", ctypes.c_int64),
+                ("min_sep", ctypes.c_double), ("t_max", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("toi", ctypes.c_double), ("t_width", ctypes.c_double),
+                ("n_checks", ctypes.c_uint64), ("hit", ctypes.c_uint8),
+                ("status", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 6)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("lane_waves_per_cu", ctypes.c_int32), ("lane_capacity", ctypes.c_int32),
+                ("lane_budget", ctypes.c_int64), ("group_waves", ctypes.c_int32),
+                ("group_count", ctypes.c_int32), ("group_capacity", ctypes.c_int64),
+                ("block_count", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("pos", ctypes.c_void_p), ("kind", ctypes.c_void_p),
+                ("default_kind", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 7),
+                ("delta_q", ctypes.c_void_p), ("max_iter_q", ctypes.c_void_p),
+                ("min_sep_q", ctypes.c_void_p), ("params", Params),
+                ("on_device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class ResultSoA(ctypes.Structure):
+    _fields_ = [("toi", ctypes.c_void_p), ("t_width", ctypes.c_void_p), ("hit", ctypes.c_void_p),
+                ("n_checks", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("checks", (ctypes.c_uint64 * 2) * 3), ("promoted", ctypes.c_uint64 * 2),
+                ("kernel_ms", ctypes.c_float * 4)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        # One HIP runtime per process: PyTorch-ROCm ships its own copy of
+        # libamdhip64.so.7.  Loading torch first makes the library bind to that
+        # copy (same soname) instead of starting a second runtime that would
+        # then find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        V, P = ctypes.c_void_p, ctypes.POINTER
+        D43 = P(ctypes.c_double * 3)
+        L.ccd_vf.argtypes = [D43, D43, P(Params), P(Result)]
+        L.ccd_ee.argtypes = [D43, D43, P(Params), P(Result)]
+        L.ccd_params_default.argtypes = [P(Params)]
+        L.ccd_params_default.restype = None
+        L.ccd_context_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(V)]
+        L.ccd_context_destroy.argtypes = [V]
+        L.ccd_context_destroy.restype = None
+        L.ccd_context_set_engine.argtypes = [V, ctypes.c_int]
+        L.ccd_context_get_tuning.argtypes = [V, P(Tuning)]
+        L.ccd_context_set_tuning.argtypes = [V, P(Tuning)]
+        L.ccd_batch.argtypes = [V, P(BatchDesc), P(ResultSoA), V]
+        L.ccd_context_enable_timing.argtypes = [V, ctypes.c_int]
+        L.ccd_context_last_stats.argtypes = [V, P(Stats)]
+        L.ccd_strerror.argtypes = [ctypes.c_int]
+        L.ccd_strerror.restype = ctypes.c_char_p
+        L.ccd_last_error.argtypes = []
+        L.ccd_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def load():
+    """Loads the HIP library (raises if it is missing)."""
+    return _lib()
+
+
+def params(delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Params:
+    p = Params()
+    _lib().ccd_params_default(ctypes.byref(p))
+    p.delta, p.max_iter, p.min_sep = float(delta), int(max_iter), float(min_sep)
+    p.flags = FLAG_LITERAL if literal else 0
+    return p
+
+
+def _single(fn, X, delta, max_iter, min_sep, literal):
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(8, 3))
+    a = ((ctypes.c_double * 3) * 4)(*[(ctypes.c_double * 3)(*X[k]) for k in range(4)])
+    b = ((ctypes.c_double * 3) * 4)(*[(ctypes.c_double * 3)(*X[k]) for k in range(4, 8)])
+    p = params(delta, max_iter, min_sep, literal)
+    r = Result()
+    D43 = ctypes.POINTER(ctypes.c_double * 3)
+    rc = fn(ctypes.cast(a, D43), ctypes.cast(b, D43), ctypes.byref(p), ctypes.byref(r))
+    if rc != OK:
+        raise CCDError(rc, "ccd single query")
+    return r
+
+
+def vf(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Result:
+    """One vertex-face query (24 doubles: p, v1, v2, v3 at t0 then at t1) on the GPU."""
+    return _single(_lib().ccd_vf, X, delta, max_iter, min_sep, literal)
+
+
+def ee(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Result:
+    """One edge-edge query (24 doubles: p1, p2, p3, p4 at t0 then at t1) on the GPU."""
+    return _single(_lib().ccd_ee, X, delta, max_iter, min_sep, literal)
+
+
+@dataclass
+class BatchResult:
+    toi: object
+    t_width: object
+    hit: object
+    n_checks: object
+    status: object
+
+
+class Context:
+    """A device context owning the library's scratch memory."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        rc = _lib().ccd_context_create(device, mem_budget_bytes, ctypes.byref(h))
+        if rc != OK:
+            raise CCDError(rc, "ccd_context_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().ccd_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_engine(self, engine: int):
+        rc = _lib().ccd_context_set_engine(self._h, engine)
+        if rc != OK:
+            raise CCDError(rc, "ccd_context_set_engine")
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _lib().ccd_context_get_tuning(self._h, ctypes.byref(t))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_ if f != "reserved"}
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        rc = _lib().ccd_context_set_tuning(self._h, ctypes.byref(t))
+        if rc != OK:
+            raise CCDError(rc, "ccd_context_set_tuning")
+
+    def enable_timing(self, on: bool = True):
+        _lib().ccd_context_enable_timing(self._h, 1 if on else 0)
+
+    def last_stats(self) -> dict:
+        s = Stats()
+        rc = _lib().ccd_context_last_stats(self._h, ctypes.byref(s))
+        out = {"checks": [[int(s.checks[t][k]) for k in range(2)] for t in range(3)],
+               "promoted": [int(s.promoted[0]), int(s.promoted[1])],
+               "kernel_ms": [float(x) for x in s.kernel_ms], "rc": rc}
+        if rc not in (OK,):
+            raise CCDError(rc, "ccd batch counters")
+        return out
+
+    # -- batches -------------------------------------------------------------
+    def batch_device(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
+                     min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
+                     out: BatchResult | None = None, stream=None) -> BatchResult:
+        """Asynchronous batch on device tensors (torch): pos float64 [24, n],
+        kind uint8 [n].  Results are torch tensors on the same device."""
+        import torch
+        assert pos.is_cuda and pos.dtype == torch.float64 and pos.dim() == 2 and pos.shape[0] == 24
+        pos = pos.contiguous()
+        n = pos.shape[1]
+        dev = pos.device
+        if out is None:
+            out = BatchResult(
+                toi=torch.empty(n, dtype=torch.float64, device=dev),
+                t_width=torch.empty(n, dtype=torch.float64, device=dev),
+                hit=torch.empty(n, dtype=torch.uint8, device=dev),
+                n_checks=torch.empty(n, dtype=torch.int64, device=dev),
+                status=torch.empty(n, dtype=torch.uint8, device=dev))
+        d = BatchDesc()
+        d.n = n
+        d.pos = pos.data_ptr()
+        keep = [pos]
+        if kind is not None:
+            kind = kind.contiguous()
+            assert kind.dtype == torch.uint8 and kind.is_cuda and kind.numel() == n
+            keep.append(kind)
+            d.kind = kind.data_ptr()
+        d.default_kind = default_kind
+        for name, arr, dt in (("delta_q", delta_q, torch.float64), ("max_iter_q", max_iter_q, torch.int64),
+                              ("min_sep_q", min_sep_q, torch.float64)):
+            if arr is not None:
+                arr = arr.contiguous()
+                assert arr.dtype == dt and arr.is_cuda and arr.numel() == n
+                keep.append(arr)
+                setattr(d, name, arr.data_ptr())
+        d.params = params(delta, max_iter, min_sep, literal)
+        d.on_device = 1
+        o = ResultSoA(out.toi.data_ptr(), out.t_width.data_ptr(), out.hit.data_ptr(),
+                      out.n_checks.data_ptr(), out.status.data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = _lib().ccd_batch(self._h, ctypes.byref(d), ctypes.byref(o),
+                              ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise CCDError(rc, "ccd_batch")
+        self._keep = keep
+        return out
+
+    def batch_host(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
+                   min_sep=0.0, literal=False, delta_q=None, max_iter_q=None,
+                   min_sep_q=None) -> BatchResult:
+        """Blocking batch on host numpy arrays; validates on the host first."""
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
+        assert pos.ndim == 2 and pos.shape[0] == 24
+        n = pos.shape[1]
+        res = BatchResult(toi=np.empty(n), t_width=np.empty(n), hit=np.empty(n, np.uint8),
+                          n_checks=np.empty(n, np.uint64), status=np.empty(n, np.uint8))
+        d = BatchDesc()
+        d.n = n
+        d.pos = pos.ctypes.data
+        keep = [pos]
+        if kind is not None:
+            kind = np.ascontiguousarray(np.asarray(kind, dtype=np.uint8))
+            keep.append(kind)
+            d.kind = kind.ctypes.data
+        d.default_kind = default_kind
+        for name, arr, dt in (("delta_q", delta_q, np.float64), ("max_iter_q", max_iter_q, np.int64),
+                              ("min_sep_q", min_sep_q, np.float64)):
+            if arr is not None:
+                arr = np.ascontiguousarray(np.asarray(arr, dtype=dt))
+                keep.append(arr)
+                setattr(d, name, arr.ctypes.data)
+        d.params = params(delta, max_iter, min_sep, literal)
+        d.on_device = 0
+        o = ResultSoA(res.toi.ctypes.data, res.t_width.ctypes.data, res.hit.ctypes.data,
+                      res.n_checks.ctypes.data, res.status.ctypes.data)
+        rc = _lib().ccd_batch(self._h, ctypes.byref(d), ctypes.byref(o), None)
+        if rc != OK:
+            raise CCDError(rc, "ccd_batch")
+        return res

@@ -1,0 +1,83 @@
+// Structures shared by the kernels and the host runtime of the CCD library.
+#pragma once
+#include <stdint.h>
+
+namespace ccd {
+
+// Device counters (uint64 each) kept in one small scratch array per context.
+enum Counter : int {
+    kCntCursor = 0,      // lane engine: next index into the query order
+    kCntOrderFront,      // partition: next VF slot
+    kCntOrderBack,       // partition: next EE slot (counts down from n)
+    kCntRecA,            // records handed from the lane engine to the group engine
+    kCntRecATake,        // group engine: next record to take
+    kCntRecB,            // records handed from the group engine to the block engine
+    kCntRecBTake,        // block engine: next record to take
+    kCntError,           // nonzero: a capacity the host guaranteed was exceeded
+    kCntChecks,          // 6 counters: checks [tier 0..2][kind 0..1]
+    kCntEnd = kCntChecks + 6,
+};
+
+// Inputs, parameters and outputs of one batch (passed by value to kernels).
+struct BatchArgs {
+    int64_t n;
+    const double* pos;          // [24][n]
+    const uint8_t* kind;        // [n] or null
+    const double* delta_q;      // [n] or null
+    const int64_t* max_iter_q;  // [n] or null
+    const double* min_sep_q;    // [n] or null
+    double delta;
+    int64_t max_iter;
+    double min_sep;
+    uint32_t flags;
+    uint32_t default_kind;
+    double* toi;
+    double* t_width;
+    uint8_t* hit;
+    uint64_t* n_checks;
+    uint8_t* status;
+    unsigned long long* counters;  // [kCntEnd]
+    const int64_t* order;          // [n] query order grouped by kind, or null (identity)
+};
+
+// A query handed from one engine to the next, at the start of a level.  The
+// level's boxes follow the header as three arrays it[cap], iu[cap], iv[cap].
+struct Record {
+    int64_t q;
+    uint64_t N;       // box checks before this level
+    double tpend;     // remembered terminal box (t_lo), +inf if none
+    double wpend;     // its w(I_t)
+    int32_t level;
+    int32_t d[3];     // bisection depth per axis on this level
+    uint32_t cnt;     // boxes on this level
+    uint32_t pad;
+};
+static_assert(sizeof(Record) == 56, "record header layout");
+constexpr int kRecordHeaderWords = 8;  // header padded to 64 bytes
+
+struct LaneCfg {
+    int32_t capacity;          // boxes per level per lane
+    int32_t persistent;        // 1: lanes pull queries from the cursor
+    uint64_t budget;           // checks after which a query is handed on
+    uint64_t* arena;           // lane frontiers: [slots][2][capacity][3][64]
+    uint64_t* records;         // promotion records, stride record_words
+    int64_t record_words;
+    int64_t record_cap;
+};
+
+struct GroupCfg {
+    int64_t capacity;          // boxes per level of one group's arena buffer
+    uint64_t* arena;           // [groups][2][3][capacity]
+    const uint64_t* in_records;
+    int64_t in_record_words;
+    int64_t in_record_cap;
+    int32_t in_count_idx;      // counter holding the number of input records
+    int32_t in_take_idx;       // counter used to take input records
+    uint64_t* out_records;     // overflow: restart records for the next engine (or null)
+    int64_t out_record_words;
+    int64_t out_record_cap;
+    int32_t out_count_idx;
+    int32_t tier;              // 1 (group) or 2 (block), for the check counters
+};
+
+}  // namespace ccd

@@ -1,0 +1,561 @@
+// Host runtime and C ABI of the MI355X CCD library (see include/ccd.h).
+//
+// A batch runs as a fixed sequence of kernels on the caller's stream:
+//   reset counters -> [partition queries by kind] -> lane engine ->
+//   group engine (wide queries handed on by the lane engine) ->
+//   block engine (queries whose frontier outgrew a group arena).
+// All scratch lives in one context, sized within the context's memory budget
+// and reused across batches (grow-only).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ccd.h"
+#include "ccd_internal.h"
+
+namespace ccd {
+template <bool P>
+__global__ void k_lane(BatchArgs a, LaneCfg c);
+template <int W>
+__global__ void k_group(BatchArgs a, GroupCfg g);
+__global__ void k_partition(BatchArgs a, int64_t* order);
+__global__ void k_reset(unsigned long long* counters);
+}  // namespace ccd
+
+using namespace ccd;
+
+namespace {
+
+constexpr double kCoordLimitHost = 1e300;
+
+thread_local char g_last_error[256] = "";
+
+// Records a failed HIP call (text available through ccd_last_error) and
+// returns false; clears HIP's sticky error state.
+bool hip_ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    (void)hipGetLastError();
+    return false;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+bool grow(DevBuf& b, size_t bytes) {
+    if (bytes <= b.bytes) return true;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (bytes == 0) return true;
+    if (!hip_ok(hipMalloc(&b.p, bytes), "hipMalloc")) return false;
+    b.bytes = bytes;
+    return true;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+}  // namespace
+
+struct ccd_context {
+    int device = 0;
+    int num_cu = 256;
+    size_t budget = 0;
+    int engine = CCD_ENGINE_PERSISTENT;
+    ccd_tuning tune{};
+    DevBuf counters, order, lane_arena, rec_a, group_arena, rec_b, block_arena;
+    DevBuf io;  // staging for host-pointer batches
+    bool timing = false;
+    hipEvent_t ev[5] = {};
+    bool have_events = false;
+    bool last_timed = false;
+    bool last_valid = false;
+};
+
+namespace {
+
+int set_device(int dev) {
+    return hip_ok(hipSetDevice(dev), "hipSetDevice") ? CCD_OK : CCD_EDEVICE;
+}
+
+void default_tuning(ccd_tuning& t, int num_cu) {
+    t.lane_waves_per_cu = 8;
+    t.lane_capacity = 32;
+    t.lane_budget = 256;
+    t.group_waves = 1;
+    t.group_count = num_cu * 4;
+    t.group_capacity = 1 << 16;
+    t.block_count = num_cu;
+    t.reserved = 0;
+}
+
+void clamp_tuning(ccd_tuning& t) {
+    t.lane_waves_per_cu = std::min(32, std::max(1, t.lane_waves_per_cu));
+    t.lane_capacity = std::min(256, std::max(8, t.lane_capacity));
+    t.lane_budget = std::max<int64_t>(1, t.lane_budget);
+    if (t.group_waves >= 8) t.group_waves = 8;
+    else if (t.group_waves >= 4) t.group_waves = 4;
+    else if (t.group_waves >= 2) t.group_waves = 2;
+    else t.group_waves = 1;
+    t.group_count = std::min(1 << 16, std::max(1, t.group_count));
+    t.group_capacity = std::min<int64_t>(int64_t(1) << 28, std::max<int64_t>(256, t.group_capacity));
+    t.block_count = std::min(1 << 12, std::max(1, t.block_count));
+}
+
+bool params_ok(const ccd_params& p) {
+    return p.t_max == 1.0 && p.reserved == 0 && (p.flags & ~CCD_FLAG_LITERAL) == 0;
+}
+
+// Host copy of the device-side query validation (same rule, same arithmetic).
+bool host_query_valid(const double X[24], int kind, double delta, int64_t max_iter, double min_sep) {
+    if (kind != CCD_KIND_VF && kind != CCD_KIND_EE) return false;
+    for (int i = 0; i < 24; ++i)
+        if (!(std::fabs(X[i]) <= kCoordLimitHost)) return false;
+    if (!(delta > 0.0) || !(delta <= 1.7976931348623157e308)) return false;
+    if (max_iter < 1) return false;
+    double gmin = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double g = 1.0;
+        for (int k = 0; k < 8; ++k) g = std::max(g, std::fabs(X[3 * k + c]));
+        gmin = (c == 0) ? g : std::min(gmin, g);
+    }
+    if (!(min_sep >= 0.0) || !(min_sep < gmin)) return false;
+    return true;
+}
+
+struct Plan {
+    int64_t n;
+    int lane_slots;
+    int lane_grid;       // blocks of 256 threads
+    int64_t rec_a_words, rec_a_cap;
+    int64_t rec_b_words, rec_b_cap;
+    int group_count;
+    int64_t group_cap;
+    int block_count;
+    int64_t block_cap;
+};
+
+int make_plan(ccd_context* ctx, int64_t n, int64_t max_iter_max, bool persistent, Plan& P) {
+    const ccd_tuning& t = ctx->tune;
+    P.n = n;
+    const int K = t.lane_capacity;
+    if (persistent) {
+        P.lane_slots = ctx->num_cu * t.lane_waves_per_cu;
+        P.lane_grid = (P.lane_slots * 64 + 255) / 256;
+        P.lane_slots = P.lane_grid * 4;
+    } else {
+        P.lane_grid = (int)((n + 255) / 256);
+        P.lane_slots = P.lane_grid * 4;
+    }
+    P.rec_a_words = kRecordHeaderWords + 3 * (int64_t)K;
+    P.rec_a_cap = n;
+    P.rec_b_words = kRecordHeaderWords + 3;
+    P.rec_b_cap = n;
+    P.group_cap = std::max<int64_t>(t.group_capacity, K);
+    P.group_count = t.group_count;
+    // the widest frontier a level can reach before Alg. 2 stops is < 2 m_I
+    P.block_cap = std::max<int64_t>(2 * max_iter_max + 2, 64);
+    P.block_count = t.block_count;
+
+    const size_t fixed = 64 * 8 + (size_t)n * 8                                // counters, order
+                         + (size_t)P.lane_slots * 2 * K * 3 * 64 * 8           // lane arenas
+                         + (size_t)P.rec_a_cap * P.rec_a_words * 8             // records A
+                         + (size_t)P.rec_b_cap * P.rec_b_words * 8;            // records B
+    const size_t per_group = (size_t)6 * P.group_cap * 8;
+    const size_t per_block = (size_t)6 * P.block_cap * 8;
+    if (fixed + per_group + per_block > ctx->budget) return CCD_ENOMEM;
+    size_t left = ctx->budget - fixed;
+    // give the block engine at most half of what is left, the group engine the rest
+    size_t blocks_fit = std::max<size_t>(1, (left / 2) / per_block);
+    P.block_count = (int)std::min<size_t>(P.block_count, blocks_fit);
+    left -= (size_t)P.block_count * per_block;
+    size_t groups_fit = std::max<size_t>(1, left / per_group);
+    P.group_count = (int)std::min<size_t>(P.group_count, groups_fit);
+    return CCD_OK;
+}
+
+int ensure_scratch(ccd_context* ctx, const Plan& P) {
+    const int K = ctx->tune.lane_capacity;
+    bool ok = grow(ctx->counters, 64 * 8) && grow(ctx->order, (size_t)P.n * 8) &&
+              grow(ctx->lane_arena, (size_t)P.lane_slots * 2 * K * 3 * 64 * 8) &&
+              grow(ctx->rec_a, (size_t)P.rec_a_cap * P.rec_a_words * 8) &&
+              grow(ctx->rec_b, (size_t)P.rec_b_cap * P.rec_b_words * 8) &&
+              grow(ctx->group_arena, (size_t)P.group_count * 6 * P.group_cap * 8) &&
+              grow(ctx->block_arena, (size_t)P.block_count * 6 * P.block_cap * 8);
+    return ok ? CCD_OK : CCD_ENOMEM;
+}
+
+int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool persistent) {
+    const int K = ctx->tune.lane_capacity;
+    a.counters = (unsigned long long*)ctx->counters.p;
+    a.order = nullptr;
+    const bool timed = ctx->timing && ctx->have_events;
+    if (timed) (void)hipEventRecord(ctx->ev[0], s);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
+    if (persistent && a.kind) {
+        hipLaunchKernelGGL(k_partition, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, a,
+                           (int64_t*)ctx->order.p);
+        a.order = (const int64_t*)ctx->order.p;
+    }
+    if (timed) (void)hipEventRecord(ctx->ev[1], s);
+    LaneCfg lc;
+    lc.capacity = K;
+    lc.persistent = persistent ? 1 : 0;
+    lc.budget = persistent ? (uint64_t)ctx->tune.lane_budget : ~0ull;
+    lc.arena = (uint64_t*)ctx->lane_arena.p;
+    lc.records = (uint64_t*)ctx->rec_a.p;
+    lc.record_words = P.rec_a_words;
+    lc.record_cap = P.rec_a_cap;
+    if (persistent)
+        hipLaunchKernelGGL(k_lane<true>, dim3(P.lane_grid), dim3(256), 0, s, a, lc);
+    else
+        hipLaunchKernelGGL(k_lane<false>, dim3(P.lane_grid), dim3(256), 0, s, a, lc);
+    if (timed) (void)hipEventRecord(ctx->ev[2], s);
+
+    GroupCfg g;
+    g.capacity = P.group_cap;
+    g.arena = (uint64_t*)ctx->group_arena.p;
+    g.in_records = (const uint64_t*)ctx->rec_a.p;
+    g.in_record_words = P.rec_a_words;
+    g.in_record_cap = P.rec_a_cap;
+    g.in_count_idx = kCntRecA;
+    g.in_take_idx = kCntRecATake;
+    g.out_records = (uint64_t*)ctx->rec_b.p;
+    g.out_record_words = P.rec_b_words;
+    g.out_record_cap = P.rec_b_cap;
+    g.out_count_idx = kCntRecB;
+    g.tier = 1;
+    switch (ctx->tune.group_waves) {
+        case 8:
+            hipLaunchKernelGGL(k_group<8>, dim3(P.group_count), dim3(512), 0, s, a, g);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_group<2>, dim3(P.group_count), dim3(128), 0, s, a, g);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_group<4>, dim3(P.group_count), dim3(256), 0, s, a, g);
+            break;
+        default:
+            hipLaunchKernelGGL(k_group<1>, dim3(P.group_count), dim3(64), 0, s, a, g);
+    }
+    if (timed) (void)hipEventRecord(ctx->ev[3], s);
+
+    GroupCfg b;
+    b.capacity = P.block_cap;
+    b.arena = (uint64_t*)ctx->block_arena.p;
+    b.in_records = (const uint64_t*)ctx->rec_b.p;
+    b.in_record_words = P.rec_b_words;
+    b.in_record_cap = P.rec_b_cap;
+    b.in_count_idx = kCntRecB;
+    b.in_take_idx = kCntRecBTake;
+    b.out_records = nullptr;
+    b.out_record_words = 0;
+    b.out_record_cap = 0;
+    b.out_count_idx = 0;
+    b.tier = 2;
+    hipLaunchKernelGGL(k_group<8>, dim3(P.block_count), dim3(512), 0, s, a, b);
+    if (timed) (void)hipEventRecord(ctx->ev[4], s);
+    ctx->last_timed = timed;
+    ctx->last_valid = true;
+    return hip_ok(hipGetLastError(), "kernel launch") ? CCD_OK : CCD_EDEVICE;
+}
+
+std::mutex g_default_mu;
+ccd_context* g_default = nullptr;
+
+int single(int kind, const double x0[4][3], const double x1[4][3], const ccd_params* p,
+           ccd_result* out) {
+    if (!x0 || !x1 || !p || !out) return CCD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default) {
+        int rc = ccd_context_create(0, (size_t)1 << 30, &g_default);
+        if (rc != CCD_OK) return rc;
+    }
+    double pos[24];
+    for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 3; ++c) {
+            pos[3 * k + c] = x0[k][c];
+            pos[3 * (k + 4) + c] = x1[k][c];
+        }
+    ccd_batch_desc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = 1;
+    d.pos = pos;
+    d.kind = nullptr;
+    d.default_kind = (uint8_t)kind;
+    d.params = *p;
+    d.on_device = 0;
+    double toi, tw;
+    uint8_t hit, st;
+    uint64_t nc;
+    ccd_result_soa o = {&toi, &tw, &hit, &nc, &st};
+    int rc = ccd_batch(g_default, &d, &o, nullptr);
+    if (rc != CCD_OK) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->toi = toi;
+    out->t_width = tw;
+    out->n_checks = nc;
+    out->hit = hit;
+    out->status = st;
+    return CCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ccd_params_default(ccd_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->delta = 1e-6;
+    p->max_iter = 1000000;
+    p->min_sep = 0.0;
+    p->t_max = 1.0;
+}
+
+const char* ccd_last_error(void) { return g_last_error; }
+
+const char* ccd_strerror(int code) {
+    switch (code) {
+        case CCD_OK: return "ok";
+        case CCD_EINVAL: return "invalid argument";
+        case CCD_ENOMEM: return "device memory budget exceeded";
+        case CCD_EDEVICE: return "HIP device error";
+        case CCD_EAGAIN: return "request does not fit now";
+        case CCD_ETIMEDOUT: return "timed out";
+        case CCD_ECANCELED: return "cancelled";
+        default: return "unknown error";
+    }
+}
+
+int ccd_context_create(int device, size_t mem_budget_bytes, ccd_context** out) {
+    if (!out) return CCD_EINVAL;
+    int ndev = 0;
+    if (!hip_ok(hipGetDeviceCount(&ndev), "hipGetDeviceCount")) return CCD_EDEVICE;
+    if (ndev <= device || device < 0) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "no HIP device %d", device);
+        return CCD_EDEVICE;
+    }
+    if (set_device(device) != CCD_OK) return CCD_EDEVICE;
+    ccd_context* c = new ccd_context();
+    c->device = device;
+    c->budget = mem_budget_bytes ? mem_budget_bytes : ((size_t)16 << 30);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    default_tuning(c->tune, c->num_cu);
+    c->have_events = true;
+    for (int i = 0; i < 5; ++i)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) c->have_events = false;
+    (void)hipGetLastError();
+    *out = c;
+    return CCD_OK;
+}
+
+void ccd_context_destroy(ccd_context* c) {
+    if (!c) return;
+    (void)set_device(c->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&c->counters, &c->order, &c->lane_arena, &c->rec_a, &c->group_arena,
+                      &c->rec_b, &c->block_arena, &c->io})
+        release(*b);
+    if (c->have_events)
+        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+}
+
+int ccd_context_set_engine(ccd_context* c, int engine) {
+    if (!c || (engine != CCD_ENGINE_PERSISTENT && engine != CCD_ENGINE_PLAIN)) return CCD_EINVAL;
+    c->engine = engine;
+    return CCD_OK;
+}
+
+int ccd_context_get_tuning(ccd_context* c, ccd_tuning* out) {
+    if (!c || !out) return CCD_EINVAL;
+    *out = c->tune;
+    return CCD_OK;
+}
+
+int ccd_context_set_tuning(ccd_context* c, const ccd_tuning* t) {
+    if (!c || !t) return CCD_EINVAL;
+    ccd_tuning n = c->tune;
+    if (t->lane_waves_per_cu) n.lane_waves_per_cu = t->lane_waves_per_cu;
+    if (t->lane_capacity) n.lane_capacity = t->lane_capacity;
+    if (t->lane_budget) n.lane_budget = t->lane_budget;
+    if (t->group_waves) n.group_waves = t->group_waves;
+    if (t->group_count) n.group_count = t->group_count;
+    if (t->group_capacity) n.group_capacity = t->group_capacity;
+    if (t->block_count) n.block_count = t->block_count;
+    clamp_tuning(n);
+    c->tune = n;
+    return CCD_OK;
+}
+
+int ccd_context_enable_timing(ccd_context* c, int enable) {
+    if (!c) return CCD_EINVAL;
+    c->timing = enable != 0;
+    return CCD_OK;
+}
+
+int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
+    if (!c || !out) return CCD_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    if (!c->last_valid) return CCD_OK;
+    if (set_device(c->device) != CCD_OK) return CCD_EDEVICE;
+    if (!hip_ok(hipDeviceSynchronize(), "hipDeviceSynchronize")) return CCD_EDEVICE;
+    unsigned long long h[kCntEnd];
+    if (!hip_ok(hipMemcpy(h, c->counters.p, sizeof(h), hipMemcpyDeviceToHost), "copy counters"))
+        return CCD_EDEVICE;
+    for (int t = 0; t < 3; ++t)
+        for (int k = 0; k < 2; ++k) out->checks[t][k] = h[kCntChecks + 2 * t + k];
+    out->promoted[0] = h[kCntRecA];
+    out->promoted[1] = h[kCntRecB];
+    if (c->last_timed)
+        for (int i = 0; i < 4; ++i) (void)hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]);
+    if (h[kCntError]) return CCD_ENOMEM;
+    return CCD_OK;
+}
+
+int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* out, void* stream) {
+    if (!ctx || !d || !out) return CCD_EINVAL;
+    if (d->n < 0 || !params_ok(d->params)) return CCD_EINVAL;
+    if (d->default_kind > 1) return CCD_EINVAL;
+    if (d->n == 0) return CCD_OK;
+    if (!d->pos || !out->toi || !out->t_width || !out->hit || !out->n_checks || !out->status)
+        return CCD_EINVAL;
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = d->n;
+    const bool persistent = ctx->engine == CCD_ENGINE_PERSISTENT;
+
+    // batch-level parameter checks that do not depend on the queries
+    int64_t mi_max = d->params.max_iter;
+    if (!d->max_iter_q && d->params.max_iter < 1) return CCD_EINVAL;
+
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.delta = d->params.delta;
+    a.max_iter = d->params.max_iter;
+    a.min_sep = d->params.min_sep;
+    a.flags = d->params.flags;
+    a.default_kind = d->default_kind;
+
+    if (!d->on_device) {
+        // validate everything on the host before touching the device
+        for (int64_t q = 0; q < n; ++q) {
+            double X[24];
+            for (int r = 0; r < 24; ++r) X[r] = d->pos[r * n + q];
+            const int kind = d->kind ? d->kind[q] : d->default_kind;
+            const double dl = d->delta_q ? d->delta_q[q] : d->params.delta;
+            const int64_t mi = d->max_iter_q ? d->max_iter_q[q] : d->params.max_iter;
+            const double ms = d->min_sep_q ? d->min_sep_q[q] : d->params.min_sep;
+            if (!host_query_valid(X, kind, dl, mi, ms)) return CCD_EINVAL;
+            if (d->max_iter_q) mi_max = std::max(mi_max, mi);
+        }
+        if (d->max_iter_q) {
+            mi_max = 1;
+            for (int64_t q = 0; q < n; ++q) mi_max = std::max(mi_max, d->max_iter_q[q]);
+        }
+        // stage inputs and outputs in device memory
+        size_t off = 0;
+        auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+        const size_t o_pos = take((size_t)24 * n * 8);
+        const size_t o_kind = d->kind ? take((size_t)n) : 0;
+        const size_t o_dq = d->delta_q ? take((size_t)n * 8) : 0;
+        const size_t o_mq = d->max_iter_q ? take((size_t)n * 8) : 0;
+        const size_t o_sq = d->min_sep_q ? take((size_t)n * 8) : 0;
+        const size_t o_toi = take((size_t)n * 8), o_tw = take((size_t)n * 8);
+        const size_t o_hit = take((size_t)n), o_nc = take((size_t)n * 8), o_st = take((size_t)n);
+        if (!grow(ctx->io, off)) return CCD_ENOMEM;
+        char* base = (char*)ctx->io.p;
+        bool ok = hip_ok(hipMemcpyAsync(base + o_pos, d->pos, (size_t)24 * n * 8, hipMemcpyHostToDevice, s), "copy pos");
+        if (ok && d->kind) ok = hip_ok(hipMemcpyAsync(base + o_kind, d->kind, n, hipMemcpyHostToDevice, s), "copy kind");
+        if (ok && d->delta_q) ok = hip_ok(hipMemcpyAsync(base + o_dq, d->delta_q, n * 8, hipMemcpyHostToDevice, s), "copy delta");
+        if (ok && d->max_iter_q) ok = hip_ok(hipMemcpyAsync(base + o_mq, d->max_iter_q, n * 8, hipMemcpyHostToDevice, s), "copy max_iter");
+        if (ok && d->min_sep_q) ok = hip_ok(hipMemcpyAsync(base + o_sq, d->min_sep_q, n * 8, hipMemcpyHostToDevice, s), "copy min_sep");
+        if (!ok) return CCD_EDEVICE;
+        a.pos = (const double*)(base + o_pos);
+        a.kind = d->kind ? (const uint8_t*)(base + o_kind) : nullptr;
+        a.delta_q = d->delta_q ? (const double*)(base + o_dq) : nullptr;
+        a.max_iter_q = d->max_iter_q ? (const int64_t*)(base + o_mq) : nullptr;
+        a.min_sep_q = d->min_sep_q ? (const double*)(base + o_sq) : nullptr;
+        a.toi = (double*)(base + o_toi);
+        a.t_width = (double*)(base + o_tw);
+        a.hit = (uint8_t*)(base + o_hit);
+        a.n_checks = (uint64_t*)(base + o_nc);
+        a.status = (uint8_t*)(base + o_st);
+        Plan P;
+        int rc = make_plan(ctx, n, mi_max, persistent, P);
+        if (rc != CCD_OK) return rc;
+        rc = ensure_scratch(ctx, P);
+        if (rc != CCD_OK) return rc;
+        rc = launch(ctx, P, a, s, persistent);
+        if (rc != CCD_OK) return rc;
+        unsigned long long err = 0;
+        ok = hip_ok(hipMemcpyAsync(out->toi, a.toi, n * 8, hipMemcpyDeviceToHost, s), "copy toi") &&
+             hip_ok(hipMemcpyAsync(out->t_width, a.t_width, n * 8, hipMemcpyDeviceToHost, s), "copy t_width") &&
+             hip_ok(hipMemcpyAsync(out->hit, a.hit, n, hipMemcpyDeviceToHost, s), "copy hit") &&
+             hip_ok(hipMemcpyAsync(out->n_checks, a.n_checks, n * 8, hipMemcpyDeviceToHost, s), "copy n_checks") &&
+             hip_ok(hipMemcpyAsync(out->status, a.status, n, hipMemcpyDeviceToHost, s), "copy status") &&
+             hip_ok(hipMemcpyAsync(&err, (unsigned long long*)ctx->counters.p + kCntError, 8,
+                                   hipMemcpyDeviceToHost, s), "copy error counter") &&
+             hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (!ok) return CCD_EDEVICE;
+        if (err) {
+            std::snprintf(g_last_error, sizeof(g_last_error), "scratch capacity exceeded");
+            return CCD_ENOMEM;
+        }
+        return CCD_OK;
+    }
+
+    // device pointers: per-query m_I must be known on the host to size the
+    // widest arena; read it back when it varies per query (synchronises)
+    if (d->max_iter_q) {
+        std::vector<int64_t> h(n);
+        if (!hip_ok(hipMemcpyAsync(h.data(), d->max_iter_q, n * 8, hipMemcpyDeviceToHost, s), "copy max_iter") ||
+            !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"))
+            return CCD_EDEVICE;
+        mi_max = 1;
+        for (int64_t v : h) mi_max = std::max(mi_max, v);
+    }
+    a.pos = d->pos;
+    a.kind = d->kind;
+    a.delta_q = d->delta_q;
+    a.max_iter_q = d->max_iter_q;
+    a.min_sep_q = d->min_sep_q;
+    a.toi = out->toi;
+    a.t_width = out->t_width;
+    a.hit = out->hit;
+    a.n_checks = out->n_checks;
+    a.status = out->status;
+    Plan P;
+    int rc = make_plan(ctx, n, std::max<int64_t>(mi_max, 1), persistent, P);
+    if (rc != CCD_OK) return rc;
+    rc = ensure_scratch(ctx, P);
+    if (rc != CCD_OK) return rc;
+    return launch(ctx, P, a, s, persistent);
+}
+
+int ccd_vf(const double x0[4][3], const double x1[4][3], const ccd_params* p, ccd_result* out) {
+    return single(CCD_KIND_VF, x0, x1, p, out);
+}
+
+int ccd_ee(const double x0[4][3], const double x1[4][3], const ccd_params* p, ccd_result* out) {
+    return single(CCD_KIND_EE, x0, x1, p, out);
+}
+
+}  // extern "C"

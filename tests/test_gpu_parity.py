@@ -1,0 +1,267 @@
+"""GPU <-> oracle parity of the HIP root finder, called through the C ABI.
+
+Bar: hit and status bit-exact, toi and t_width bit-identical (which implies
+the stated tolerance |toi_gpu - toi_oracle| <= 1e-6), n_checks identical.
+Both sides compute in binary64 with the same operation order and no
+contraction, so any difference is a bug."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_13349_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("toi", "t_width", "hit", "n_checks", "status")
+TOI_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ccdmod():
+    from paper_2009_13349_amd import ccd
+    ccd.load()
+    return ccd
+
+
+@pytest.fixture()
+def ctx(ccdmod, torch_dev):
+    c = ccdmod.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, torch_dev, w, engine=0, **kw):
+    torch, dev = torch_dev
+    ctx.set_engine(engine)
+    pos = torch.from_numpy(np.ascontiguousarray(w["pos"])).to(dev)
+    kind = torch.from_numpy(np.ascontiguousarray(w["kind"])).to(dev)
+    extra = {}
+    for name, dt in (("delta_q", torch.float64), ("max_iter_q", torch.int64), ("min_sep_q", torch.float64)):
+        if kw.get(name) is not None:
+            extra[name] = torch.from_numpy(np.ascontiguousarray(kw.pop(name))).to(dev, dt)
+        else:
+            kw.pop(name, None)
+    r = ctx.batch_device(pos, kind, **kw, **extra)
+    torch.cuda.synchronize()
+    out = {k: getattr(r, k).cpu().numpy() for k in FIELDS}
+    out["n_checks"] = out["n_checks"].astype(np.uint64)
+    return out
+
+
+def run_oracle(w, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False, delta_q=None,
+               max_iter_q=None, min_sep_q=None):
+    return oracle.solve_batch(w["pos"], w["kind"], delta=delta if delta_q is None else delta_q,
+                              max_iter=max_iter if max_iter_q is None else max_iter_q,
+                              min_sep=min_sep if min_sep_q is None else min_sep_q, literal=literal)
+
+
+def assert_same(got, ref, idx=None, what=""):
+    for k in FIELDS:
+        g = got[k] if idx is None else got[k][idx]
+        r = ref[k]
+        if k in ("toi", "t_width"):
+            gb = np.ascontiguousarray(g, dtype=np.float64).view(np.int64)
+            rb = np.ascontiguousarray(r, dtype=np.float64).view(np.int64)
+            bad = np.nonzero(gb != rb)[0]
+        else:
+            bad = np.nonzero(np.asarray(g).astype(np.int64) != np.asarray(r).astype(np.int64))[0]
+        assert len(bad) == 0, (f"{what}: field {k} differs at {len(bad)} queries, first "
+                               f"{bad[:5].tolist()}: gpu {np.asarray(g)[bad[:5]]} oracle {np.asarray(r)[bad[:5]]}")
+    fin = np.isfinite(ref["toi"])
+    g = got["toi"] if idx is None else got["toi"][idx]
+    assert np.all(np.abs(g[fin] - ref["toi"][fin]) <= TOI_TOL)
+
+
+# ---------------------------------------------------------------------------
+
+def test_single_queries_hand_cases(ccdmod, torch_dev):
+    from tests.test_oracle_cases import CASES
+    for name, kind, X, min_sep, _, _ in CASES:
+        fn = ccdmod.vf if kind == 0 else ccdmod.ee
+        g = fn(X, 1e-6, 1_000_000, min_sep)
+        r = oracle.solve(kind, X, 1e-6, 1_000_000, min_sep)
+        assert (g.toi, g.t_width, g.n_checks, g.hit, g.status) == \
+            (r.toi, r.t_width, r.n_checks, r.hit, r.status), name
+
+
+def test_single_queries_paper_examples(ccdmod, torch_dev):
+    from tests.test_oracle_pins import _paper_examples
+    for name, (_, kind, X, _) in _paper_examples().items():
+        fn = ccdmod.vf if kind == 0 else ccdmod.ee
+        g = fn(X)
+        r = oracle.solve(kind, X)
+        assert (g.toi, g.t_width, g.n_checks, g.hit, g.status) == \
+            (r.toi, r.t_width, r.n_checks, r.hit, r.status), name
+
+
+@pytest.mark.parametrize("engine", [0, 1], ids=["persistent", "plain"])
+def test_uniform_vf_4096(ctx, torch_dev, engine):
+    w = W.uniform_vf(4096, seed=0)
+    got = run_gpu(ctx, torch_dev, w, engine)
+    ref = run_oracle(w)
+    assert_same(got, ref, what="uniform_vf_4096")
+    assert ref["hit"][1::2].all()  # every constructed crossing is found
+
+
+@pytest.mark.parametrize("engine", [0, 1], ids=["persistent", "plain"])
+def test_edge_edge_degenerate(ctx, torch_dev, engine):
+    w = W.edge_edge_mixed(3000, seed=1)
+    got = run_gpu(ctx, torch_dev, w, engine, max_iter=100_000)
+    ref = run_oracle(w, max_iter=100_000)
+    assert_same(got, ref, what="edge_edge_mixed_3000")
+    assert (ref["status"] & 1).sum() > 50  # the degenerate tail reaches the cap
+
+
+def test_edge_edge_degenerate_paper_cap(ctx, torch_dev):
+    w = W.edge_edge_mixed(400, seed=5, degenerate_frac=0.1)
+    got = run_gpu(ctx, torch_dev, w, 0, max_iter=1_000_000)
+    ref = run_oracle(w, max_iter=1_000_000)
+    assert_same(got, ref, what="edge_edge_mixed_400 m_I=1e6")
+
+
+@pytest.mark.parametrize("engine", [0, 1], ids=["persistent", "plain"])
+def test_simulation_sample(ctx, torch_dev, engine):
+    w = W.simulation_mixed(20000, seed=2)
+    got = run_gpu(ctx, torch_dev, w, engine)
+    ref = run_oracle(w)
+    assert_same(got, ref, what="simulation_mixed_20000")
+
+
+@pytest.mark.parametrize("d_min,delta", [(1e-4, 1e-6), (1e-3, 1e-4), (1e-4, 1e-4), (1e-3, 1e-6)])
+def test_min_separation(ctx, torch_dev, d_min, delta):
+    w = W.min_separation(1500, seed=3, d_min=d_min, delta=delta)
+    got = run_gpu(ctx, torch_dev, w, 0, delta=delta, min_sep=d_min, max_iter=100_000)
+    ref = run_oracle(w, delta=delta, min_sep=d_min, max_iter=100_000)
+    assert_same(got, ref, what=f"min_sep d={d_min} delta={delta}")
+
+
+def test_literal_mode(ctx, torch_dev):
+    w = W.concat([W.edge_edge_mixed(1500, seed=7), W.uniform_vf(500, seed=8)])
+    got = run_gpu(ctx, torch_dev, w, 0, max_iter=50_000, literal=True)
+    ref = run_oracle(w, max_iter=50_000, literal=True)
+    assert_same(got, ref, what="literal")
+
+
+def test_per_query_parameters(ctx, torch_dev):
+    w = W.concat([W.uniform_vf(800, seed=9), W.edge_edge_mixed(800, seed=10)])
+    n = w["pos"].shape[1]
+    rng = np.random.default_rng(0)
+    dq = np.exp(rng.uniform(np.log(1e-6), np.log(1e-3), n))
+    mq = rng.integers(1, 50_000, n).astype(np.int64)
+    sq = np.where(rng.uniform(size=n) < 0.3, rng.uniform(1e-5, 1e-3, n), 0.0)
+    got = run_gpu(ctx, torch_dev, w, 0, delta_q=dq, max_iter_q=mq, min_sep_q=sq)
+    ref = run_oracle(w, delta_q=dq, max_iter_q=mq, min_sep_q=sq)
+    assert_same(got, ref, what="per-query parameters")
+
+
+def test_results_independent_of_tuning_and_engine(ctx, torch_dev):
+    """Tiny lane arenas, a one-check budget and small group arenas force every
+    query through the hand-off paths; the bits must not change."""
+    w = W.concat([W.uniform_vf(1000, seed=11), W.edge_edge_mixed(1000, seed=12)])
+    base = run_gpu(ctx, torch_dev, w, 0, max_iter=200_000)
+    ref = run_oracle(w, max_iter=200_000)
+    assert_same(base, ref, what="default tuning")
+    for tune in ({"lane_capacity": 8, "lane_budget": 1},
+                 {"lane_capacity": 8, "group_capacity": 256, "group_waves": 4},
+                 {"lane_waves_per_cu": 1, "group_count": 3, "block_count": 2, "group_waves": 2},
+                 {"lane_budget": 100000, "lane_capacity": 256, "group_waves": 8}):
+        ctx.set_tuning(**tune)
+        for engine in (0, 1):
+            got = run_gpu(ctx, torch_dev, w, engine, max_iter=200_000)
+            assert_same(got, ref, what=f"tuning {tune} engine {engine}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 257, 1031])
+def test_ragged_sizes(ctx, torch_dev, n):
+    w = W.concat([W.uniform_vf(n, seed=13), W.edge_edge_mixed(n, seed=14)])
+    w = W.subset(w, np.random.default_rng(n).permutation(2 * n)[:n])
+    for engine in (0, 1):
+        got = run_gpu(ctx, torch_dev, w, engine, max_iter=100_000)
+        ref = run_oracle(w, max_iter=100_000)
+        assert_same(got, ref, what=f"n={n} engine={engine}")
+
+
+def test_invalid_queries_on_device(ctx, torch_dev):
+    w = W.uniform_vf(64, seed=15)
+    w["pos"] = w["pos"].copy()
+    w["pos"][3, 5] = np.nan
+    w["pos"][7, 9] = np.inf
+    w["pos"][0, 11] = 2e300
+    dq = np.full(64, 1e-6)
+    dq[20] = 0.0
+    dq[21] = -1.0
+    mq = np.full(64, 1000, np.int64)
+    mq[30] = 0
+    sq = np.zeros(64)
+    sq[40] = 10.0  # not below gamma
+    got = run_gpu(ctx, torch_dev, w, 0, delta_q=dq, max_iter_q=mq, min_sep_q=sq)
+    ref = run_oracle(w, delta_q=dq, max_iter_q=mq, min_sep_q=sq)
+    bad = np.array([5, 9, 11, 20, 21, 30, 40])
+    assert np.all(got["status"][bad] == 0x80) and np.all(got["hit"][bad] == 0)
+    assert np.all(np.isnan(got["toi"][bad]))
+    ok = np.setdiff1d(np.arange(64), bad)
+    assert np.all(ref["status"][bad] == 0xFF)
+    sub = {k: ref[k][ok] for k in FIELDS}
+    assert_same(got, sub, idx=ok, what="valid queries next to invalid ones")
+
+
+def test_host_batch_validates_before_launch(ccdmod, ctx, torch_dev):
+    w = W.uniform_vf(32, seed=16)
+    res = ctx.batch_host(w["pos"], w["kind"], max_iter=10_000)
+    ref = run_oracle(w, max_iter=10_000)
+    assert_same({k: getattr(res, k) for k in FIELDS}, ref, what="host batch")
+    pos = w["pos"].copy()
+    pos[2, 3] = np.nan
+    with pytest.raises(ccdmod.CCDError) as e:
+        ctx.batch_host(pos, w["kind"])
+    assert e.value.code == ccdmod.EINVAL
+    with pytest.raises(ccdmod.CCDError):
+        ctx.batch_host(w["pos"], w["kind"], delta=0.0)
+
+
+def test_repeatable(ctx, torch_dev):
+    w = W.simulation_mixed(50_000, seed=17)
+    a = run_gpu(ctx, torch_dev, w, 0)
+    b = run_gpu(ctx, torch_dev, w, 0)
+    c = run_gpu(ctx, torch_dev, w, 1)
+    assert_same(a, b, what="repeat")
+    assert_same(a, c, what="plain vs persistent")
+
+
+def test_full_size_simulation_sampled(ctx, torch_dev):
+    """1M simulation-shaped queries at delta = 1e-6 in the benchmark's launch
+    configuration; a seeded sample (every class represented) is checked
+    against the oracle query by query."""
+    w = W.simulation_mixed(1_000_000, seed=2)
+    got = run_gpu(ctx, torch_dev, w, 0)
+    rng = np.random.default_rng(99)
+    idx = np.concatenate([rng.choice(np.nonzero(w["cls"] == c)[0], size=min(k, int((w["cls"] == c).sum())),
+                                     replace=False) for c, k in ((0, 1500), (8, 40), (9, 200))])
+    ws = W.subset(w, idx)
+    ref = run_oracle(ws)
+    assert_same(got, ref, idx=idx, what="simulation_mixed_1M sample")
+    # every grazing contact (exact touching) is reported
+    assert got["hit"][w["cls"] == 9].all()
+
+
+def test_full_size_edge_edge_sampled(ctx, torch_dev):
+    w = W.edge_edge_mixed(100_000, seed=1)
+    got = run_gpu(ctx, torch_dev, w, 0)
+    rng = np.random.default_rng(98)
+    idx = np.concatenate([rng.choice(np.nonzero(w["cls"] == c)[0], size=k, replace=False)
+                          for c, k in ((0, 400), (1, 400), (2, 8), (3, 8), (4, 8), (5, 8), (6, 8), (7, 8))])
+    ws = W.subset(w, idx)
+    ref = run_oracle(ws)
+    assert_same(got, ref, idx=idx, what="edge_edge_mixed_100k sample")
+    # constructed crossings are always found
+    assert got["hit"][w["cls"] == 1].all()
