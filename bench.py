@@ -1,0 +1,203 @@
+"""Benchmark of the MI355X CCD root finder.
+
+One step = one ccd_batch call over the whole workload (all queries resident in
+HBM before the timed region), i.e. the complete root finder for every query:
+kind partition, lane engine, group engine and block engine.  Default
+workload: 1,000,000 simulation-shaped queries (60% vertex-face, 40%
+edge-edge, 2% near-contacts, 1% grazing contacts), delta = 1e-6, m_I = 1e6,
+no minimum separation.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CCD queries/s at delta=1e-6 (persistent vs plain kernel); p50/p99 serve latency"
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk (FMA = 2)
+FLOP_PER_CHECK = {0: 227.0, 1: 177.0}  # vertex-face, edge-edge box check (binary64 add/sub/mul)
+KERNELS = ("partition", "lane", "group", "block")
+
+
+def make_workload(name: str, n: int | None):
+    from paper_2009_13349_amd import workloads as W
+    if name == "simulation":
+        return W.simulation_mixed(n or 1_000_000, seed=2)
+    if name == "edge_edge":
+        return W.edge_edge_mixed(n or 100_000, seed=1)
+    if name == "uniform_vf":
+        return W.uniform_vf(n or 4096, seed=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup):
+    from paper_2009_13349_amd import ccd
+    ctx.set_engine(engine)
+    ctx.enable_timing(True)
+    out = None
+    kw = dict(delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    for _ in range(warmup):
+        out = ctx.batch_device(pos, kind, out=out, **kw)
+        ctx.last_stats()
+    torch.cuda.synchronize()
+    per_step = []
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.batch_device(pos, kind, out=out, **kw)
+        stats.append(ctx.last_stats())  # synchronises; reads the per-kernel HIP events
+        per_step.append(time.perf_counter())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    del ccd
+    return (t1 - t0), stats, out
+
+
+def roofline(stats, kind_counts):
+    """Dominant kernel (largest device time) and its achieved FP64 rate:
+    algorithmic FLOPs (box checks executed by that kernel x FLOPs per check)
+    per launch / average launch duration from HIP events."""
+    ms = np.array([s["kernel_ms"] for s in stats])  # [steps, 4]
+    avg = ms.mean(axis=0)
+    k = int(np.argmax(avg[1:])) + 1
+    tier = k - 1
+    checks = np.array([s["checks"][tier] for s in stats], dtype=np.float64).mean(axis=0)
+    flops = checks[0] * FLOP_PER_CHECK[0] + checks[1] * FLOP_PER_CHECK[1]
+    achieved = flops / (avg[k] * 1e-3) / 1e12
+    return {
+        "bound": "alu",
+        "kernel": KERNELS[k],
+        "achieved": round(achieved, 3),
+        "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
+        "traffic": None,
+        "avg_launch_ms": round(float(avg[k]), 4),
+        "checks_per_launch": [int(checks[0]), int(checks[1])],
+        "kernel_ms_avg": {KERNELS[i]: round(float(avg[i]), 4) for i in range(4)},
+    }
+
+
+def cpu_baseline(w, seconds: float):
+    """The oracle (single thread, as it stands) on a seeded random sample of
+    the same workload, scaled to queries/s."""
+    import oracle
+    from paper_2009_13349_amd import workloads as W
+    n = w["pos"].shape[1]
+    rng = np.random.default_rng(1234)
+    perm = rng.permutation(n)
+    done, t_used, chunk = 0, 0.0, 2000
+    while t_used < seconds and done < n:
+        idx = perm[done:done + chunk]
+        ws = W.subset(w, idx)
+        t0 = time.perf_counter()
+        oracle.solve_batch(ws["pos"], ws["kind"], delta=w["delta"], max_iter=w["max_iter"],
+                           min_sep=w["min_sep"])
+        t_used += time.perf_counter() - t0
+        done += len(idx)
+    return {"value": round(done / t_used, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} queries drawn uniformly at random (seed 1234) from the same "
+                      f"{n}-query workload, single-threaded C++ oracle, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="simulation", choices=["simulation", "edge_edge", "uniform_vf"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tuning", default="", help="k=v,... overrides of ccd_tuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the root finder has no cross-GPU step in this "
+              "build (queries are independent; sharding is a partition of the query index).",
+              file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_2009_13349_amd import ccd
+
+    w = make_workload(args.workload, args.n)
+    n = w["pos"].shape[1]
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    kind = torch.from_numpy(w["kind"]).to(dev)
+    torch.cuda.synchronize()
+    kind_counts = np.bincount(w["kind"], minlength=2)
+
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    ctx = ccd.Context(0, mem_budget_bytes=32 << 30)
+    if args.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+    t_p, stats_p, out = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps,
+                                   args.warmup)
+    hits = int(out.hit.sum().item())
+    # checks the sequential Alg. 2 performs (n_checks is exact unless capped)
+    nck = out.n_checks.to(torch.float64)
+    alg_checks = [float((nck * (kind == k)).sum().item()) for k in (0, 1)]
+    value = n * args.steps / t_p
+    plain = None
+    if not args.no_plain:
+        t_b, stats_b, _ = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PLAIN, args.steps,
+                                     args.warmup)
+        plain = {"value": round(n * args.steps / t_b, 1), "ms_per_step": round(1e3 * t_b / args.steps, 3),
+                 "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
+                                   for i in range(4)}}
+    rl = roofline(stats_p, kind_counts)
+    checks_total = int(sum(sum(c) for c in stats_p[-1]["checks"]))
+    alg_flops = alg_checks[0] * FLOP_PER_CHECK[0] + alg_checks[1] * FLOP_PER_CHECK[1]
+    path_alg_tflops = alg_flops / (t_p / args.steps) / 1e12
+    ctx.close()
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_p / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "queries": n, "vf": int(kind_counts[0]),
+                   "ee": int(kind_counts[1]), "delta": w["delta"], "max_iter": w["max_iter"],
+                   "min_sep": w["min_sep"], "engine": "persistent", "parallelism": "single GPU"},
+        "plain_kernel": plain,
+        "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
+        "hits": hits,
+        "box_checks_per_step": checks_total,
+        "sequential_checks_per_step": int(sum(alg_checks)),
+        "path_algorithmic_tflops": round(path_alg_tflops, 3),
+        "promoted_per_step": stats_p[-1]["promoted"],
+        "lane_utilization": [round(sum(stats_p[-1]["checks"][i]) / stats_p[-1]["lane_slots"][i], 3)
+                             if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
+        "roofline": rl,
+    }
+    line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

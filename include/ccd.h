@@ -138,7 +138,8 @@ typedef struct ccd_tuning {
     int32_t group_count;          /* resident groups of the wide-query kernel */
     int64_t group_capacity;       /* boxes per level of a group's arena */
     int32_t block_count;          /* resident blocks of the huge-query kernel */
-    int32_t reserved;
+    int32_t group_occupancy;      /* single-wave groups: minimum waves per SIMD the register
+                                     allocation must allow (1..4) */
 } ccd_tuning;
 int ccd_context_get_tuning(ccd_context* ctx, ccd_tuning* out);
 int ccd_context_set_tuning(ccd_context* ctx, const ccd_tuning* t);
@@ -188,6 +189,8 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa
 typedef struct ccd_stats {
     uint64_t checks[3][2];   /* box checks executed by tier [lane, group, block] x kind [VF, EE] */
     uint64_t promoted[2];    /* queries handed to the group tier, to the block tier */
+    uint64_t lane_slots[3];  /* lane-iterations spent per tier; checks / lane_slots is the
+                                fraction of SIMD lanes doing box checks */
     float kernel_ms[4];      /* device time of [partition, lane, group, block] kernels
                                 (only when timing is enabled, else 0) */
 } ccd_stats;

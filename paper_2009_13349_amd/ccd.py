@@ -55,7 +55,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("lane_waves_per_cu", ctypes.c_int32), ("lane_capacity", ctypes.c_int32),
                 ("lane_budget", ctypes.c_int64), ("group_waves", ctypes.c_int32),
                 ("group_count", ctypes.c_int32), ("group_capacity", ctypes.c_int64),
-                ("block_count", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block_count", ctypes.c_int32), ("group_occupancy", ctypes.c_int32)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -73,7 +73,7 @@ class ResultSoA(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("checks", (ctypes.c_uint64 * 2) * 3), ("promoted", ctypes.c_uint64 * 2),
-                ("kernel_ms", ctypes.c_float * 4)]
+                ("lane_slots", ctypes.c_uint64 * 3), ("kernel_ms", ctypes.c_float * 4)]
 
 
 _LIB = None
@@ -197,7 +197,7 @@ class Context:
     def tuning(self) -> dict:
         t = Tuning()
         _lib().ccd_context_get_tuning(self._h, ctypes.byref(t))
-        return {f: getattr(t, f) for f, _ in Tuning._fields_ if f != "reserved"}
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
     def set_tuning(self, **kw):
         t = Tuning()
@@ -215,6 +215,7 @@ class Context:
         rc = _lib().ccd_context_last_stats(self._h, ctypes.byref(s))
         out = {"checks": [[int(s.checks[t][k]) for k in range(2)] for t in range(3)],
                "promoted": [int(s.promoted[0]), int(s.promoted[1])],
+               "lane_slots": [int(x) for x in s.lane_slots],
                "kernel_ms": [float(x) for x in s.kernel_ms], "rc": rc}
         if rc not in (OK,):
             raise CCDError(rc, "ccd batch counters")

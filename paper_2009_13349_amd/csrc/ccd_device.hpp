@@ -54,20 +54,20 @@ __device__ __forceinline__ void filter_eps(int kind, const double* X, double min
     *gamma_min = gmin;
 }
 
-// The 8 corner values of coordinate c of F over the box [t0,t1]x[u0,u1]x[v0,v1].
-// f[(a<<2)|(b<<1)|e] = F^c(t_a, u_b, v_e).  Positions at t0 and t1 are shared
-// between the corners (same bits as evaluating each corner on its own).
+// The 8 corner values of one coordinate of F over the box [t0,t1]x[u0,u1]x[v0,v1],
+// from that coordinate of the 8 points: xc[k], points 0..3 at t = 0, 4..7 at
+// t = 1.  f[(a<<2)|(b<<1)|e] = F(t_a, u_b, v_e).  Positions at t0 and t1 are
+// shared between the corners (same bits as evaluating each corner on its own).
 template <int KIND>
-__device__ __forceinline__ void corner_values(const double* X, int c, double t0, double t1,
-                                              double u0, double u1, double v0, double v1,
-                                              double f[8]) {
+__device__ __forceinline__ void corner_values_axis(const double xc[8], double t0, double t1,
+                                                   double u0, double u1, double v0, double v1,
+                                                   double f[8]) {
     const double s0 = 1.0 - t0, s1 = 1.0 - t1;
     double P[2][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double a = X[3 * k + c], b = X[3 * (k + 4) + c];
-        P[0][k] = s0 * a + t0 * b;
-        P[1][k] = s1 * a + t1 * b;
+        P[0][k] = s0 * xc[k] + t0 * xc[k + 4];
+        P[1][k] = s1 * xc[k] + t1 * xc[k + 4];
     }
     const double uu[2] = {u0, u1};
     const double vv[2] = {v0, v1};
@@ -103,6 +103,17 @@ __device__ __forceinline__ void corner_values(const double* X, int c, double t0,
                     f[(a << 2) | (b << 1) | e] = P[a][0] - face;
                 }
     }
+}
+
+// Coordinate c of F at the 8 corners, with the query as X[3k + c].
+template <int KIND>
+__device__ __forceinline__ void corner_values(const double* X, int c, double t0, double t1,
+                                              double u0, double u1, double v0, double v1,
+                                              double f[8]) {
+    double xc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xc[k] = X[3 * k + c];
+    corner_values_axis<KIND>(xc, t0, t1, u0, u1, v0, v1, f);
 }
 
 struct CheckResult {
@@ -174,6 +185,13 @@ __device__ __forceinline__ int split_axis(const double kappa[3], double wt, doub
 
 // 2^-d for 0 <= d <= 60 (exact).
 __device__ __forceinline__ double pow2neg(int d) { return __longlong_as_double((int64_t)(1023 - d) << 52); }
+
+// i * 2^-d for 0 <= i < 2^52, 0 <= d <= 52, exactly: the bit pattern
+// 2^(52-d) | i is the double 2^(52-d) + i 2^-d, and subtracting 2^(52-d)
+// (same exponent, representable result) is exact.  bias = 2^(52-d).
+__device__ __forceinline__ double dyadic(uint64_t i, int64_t bias_bits, double bias) {
+    return __longlong_as_double(bias_bits | (int64_t)i) - bias;
+}
 
 // Lexicographic order of (t, u, v) box indices of one level.
 __device__ __forceinline__ bool key_less(uint64_t at, uint64_t au, uint64_t av, uint64_t bt,

@@ -15,7 +15,8 @@ enum Counter : int {
     kCntRecBTake,        // block engine: next record to take
     kCntError,           // nonzero: a capacity the host guaranteed was exceeded
     kCntChecks,          // 6 counters: checks [tier 0..2][kind 0..1]
-    kCntEnd = kCntChecks + 6,
+    kCntSlots = kCntChecks + 6,  // 3 counters: lane slots spent per tier (utilisation)
+    kCntEnd = kCntSlots + 3,
 };
 
 // Inputs, parameters and outputs of one batch (passed by value to kernels).

@@ -49,6 +49,8 @@ struct State {
 
 struct LevelInfo {
     double wt, wu, wv;
+    int64_t bt_bits, bu_bits, bv_bits;  // bit patterns of 2^(52-d) per axis (see dyadic())
+    double bt_val, bu_val, bv_val;      // 2^(52-d) per axis
     int axis;
     bool dcap;  // the split axis is at the depth limit: every colliding box is terminal
 };
@@ -87,6 +89,12 @@ __device__ __forceinline__ LevelInfo level_info(const double kappa[3], const int
     L.wt = pow2neg(d[0]);
     L.wu = pow2neg(d[1]);
     L.wv = pow2neg(d[2]);
+    L.bt_bits = (int64_t)(1023 + 52 - d[0]) << 52;
+    L.bu_bits = (int64_t)(1023 + 52 - d[1]) << 52;
+    L.bv_bits = (int64_t)(1023 + 52 - d[2]) << 52;
+    L.bt_val = __longlong_as_double(L.bt_bits);
+    L.bu_val = __longlong_as_double(L.bu_bits);
+    L.bv_val = __longlong_as_double(L.bv_bits);
     L.axis = split_axis(kappa, L.wt, L.wu, L.wv);
     L.dcap = d[L.axis] >= kMaxDepth;
     return L;
@@ -101,13 +109,15 @@ __device__ __forceinline__ void acc_init(Acc& A) {
     A.thave = 0;
 }
 
+// track_max: the largest colliding key is only needed on a level where the
+// m_I stop can fire (N + |level| >= m_I), a level-uniform condition.
 __device__ __forceinline__ void acc_add(Acc& A, uint64_t bt, uint64_t bu, uint64_t bv, bool term,
-                                        bool small) {
+                                        bool small, bool track_max = true) {
     if (!(A.fflags & 1u) || key_less(bt, bu, bv, A.ft, A.fu, A.fv)) {
         A.ft = bt; A.fu = bu; A.fv = bv;
         A.fflags = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
     }
-    if (!A.mhave || key_less(A.mt, A.mu, A.mv, bt, bu, bv)) {
+    if (track_max && (!A.mhave || key_less(A.mt, A.mu, A.mv, bt, bu, bv))) {
         A.mt = bt; A.mu = bu; A.mv = bv;
         A.mhave = 1;
     }
@@ -131,28 +141,29 @@ __device__ __forceinline__ void acc_merge(Acc& A, const Acc& B) {
     }
 }
 
-__device__ __forceinline__ bool need_rank(const Acc& A, const State& S, const Query& Q,
-                                          const LevelInfo& L) {
+__device__ __forceinline__ bool need_rank(const Acc& A, const State& S, bool literal,
+                                          int64_t max_iter, const LevelInfo& L) {
     if (!(A.fflags & 1u)) return false;
     const double tf = (double)A.ft * L.wt;
-    const bool carry_ret = !Q.literal && S.tpend <= tf;
-    const bool cap_possible = S.N + S.cnt >= (uint64_t)Q.max_iter;
+    const bool carry_ret = !literal && S.tpend <= tf;
+    const bool cap_possible = S.N + S.cnt >= (uint64_t)max_iter;
     return carry_ret || cap_possible || (A.fflags & 2u);
 }
 
 // The level's decision (Alg. 2 replayed over one level).  rf / rm: number of
 // keys on the level below the smallest / largest colliding key (only read when
 // need_rank() said so).
-__device__ __forceinline__ Outcome decide(const Acc& A, const State& S, const Query& Q,
-                                          const LevelInfo& L, uint64_t rf, uint64_t rm) {
+__device__ __forceinline__ Outcome decide(const Acc& A, const State& S, bool literal,
+                                          int64_t max_iter, const LevelInfo& L, uint64_t rf,
+                                          uint64_t rm) {
     Outcome O;
     O.finish = true;
-    const uint64_t mI = (uint64_t)Q.max_iter;
+    const uint64_t mI = (uint64_t)max_iter;
     if (!(A.fflags & 1u)) {
         // nothing collides: the queue empties after this level
         const uint64_t n = S.N + S.cnt;
         O.n = n < mI ? n : mI;
-        if (!Q.literal && S.tpend < INFINITY) {
+        if (!literal && S.tpend < INFINITY) {
             O.toi = S.tpend; O.tw = S.wpend; O.st = kStCarry;
         } else {
             O.toi = INFINITY; O.tw = 0.0; O.st = 0;
@@ -162,7 +173,7 @@ __device__ __forceinline__ Outcome decide(const Acc& A, const State& S, const Qu
     const double tf = (double)A.ft * L.wt;
     const bool cap_possible = S.N + S.cnt >= mI;
     const uint64_t nf = S.N + rf + 1;
-    if (!Q.literal && S.tpend <= tf) {
+    if (!literal && S.tpend <= tf) {
         O.toi = S.tpend; O.tw = S.wpend; O.n = nf < mI ? nf : mI; O.st = kStCarry;
         return O;
     }
@@ -183,9 +194,9 @@ __device__ __forceinline__ Outcome decide(const Acc& A, const State& S, const Qu
 }
 
 // Moves S to the next level (after decide() returned finish = false).
-__device__ __forceinline__ void advance(State& S, const Acc& A, const Query& Q, const LevelInfo& L,
+__device__ __forceinline__ void advance(State& S, const Acc& A, bool literal, const LevelInfo& L,
                                         uint32_t next_cnt) {
-    if (!Q.literal && A.thave) {
+    if (!literal && A.thave) {
         const double tm = (double)A.tm * L.wt;
         if (tm < S.tpend) {
             S.tpend = tm;
@@ -218,11 +229,11 @@ template <int KIND>
 __device__ __forceinline__ CheckResult check_key(const Query& Q, const LevelInfo& L, uint64_t bt,
                                                  uint64_t bu, uint64_t bv, bool root,
                                                  double kappa_out[3]) {
-    const double t0 = (double)bt * L.wt, t1 = (double)(bt + 1) * L.wt;
-    const double u0 = (double)bu * L.wu, u1 = (double)(bu + 1) * L.wu;
-    const double v0 = (double)bv * L.wv, v1 = (double)(bv + 1) * L.wv;
-    return box_check<KIND>(Q.X, t0, t1, u0, u1, v0, v1, Q.eps, Q.min_sep, Q.delta, root,
-                           kappa_out);
+    const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
+    const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
+    const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
+    return box_check<KIND>(Q.X, t0, t0 + L.wt, u0, u0 + L.wu, v0, v0 + L.wv, Q.eps, Q.min_sep,
+                           Q.delta, root, kappa_out);
 }
 
 __device__ __forceinline__ CheckResult check_any(const Query& Q, const LevelInfo& L, uint64_t bt,
@@ -232,9 +243,75 @@ __device__ __forceinline__ CheckResult check_any(const Query& Q, const LevelInfo
     return check_key<kVF>(Q, L, bt, bu, bv, root, kappa_out);
 }
 
+// ---------------------------------------------------------------------------
+// Group-engine box check: the query's coordinates sit in LDS as Xs[c*8 + k]
+// (one query per block), axes are evaluated one after the other and the
+// remaining axes are skipped once no active lane of the wavefront still
+// collides (Sec. 4.2: "check one axis at a time and return early").  The
+// values are the same as box_check()'s.
+template <int KIND>
+__device__ __forceinline__ CheckResult check_box_lds(const double* Xs, const double* Es,
+                                                     double t0, double t1, double u0, double u1,
+                                                     double v0, double v1, double min_sep,
+                                                     double delta) {
+    bool col = true, ins = true;
+    double width = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        if (__ballot(col) == 0) break;
+        double xc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xc[k] = Xs[c * 8 + k];
+        double f[8];
+        corner_values_axis<KIND>(xc, t0, t1, u0, u1, v0, v1, f);
+        double m = f[0], M = f[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+            m = fmin(m, f[i]);
+            M = fmax(M, f[i]);
+        }
+        const double e = Es[c];
+        const double lo = m - min_sep;
+        const double hi = M + min_sep;
+        col = col && (lo <= e) && (hi >= -e);
+        ins = ins && (lo >= -e) && (hi <= e);
+        width = fmax(width, M - m);
+    }
+    CheckResult r;
+    r.collide = col;
+    r.small = (width < delta) || ins;
+    return r;
+}
+
+// eq. kappas from the level-0 corners, with the coordinates in LDS.
+template <int KIND>
+__device__ __forceinline__ void kappa_lds(const double* Xs, double kappa[3]) {
+    double kt = 0.0, ku = 0.0, kv = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        double xc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xc[k] = Xs[c * 8 + k];
+        double f[8];
+        corner_values_axis<KIND>(xc, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int jt = j;
+            const int ju = ((j >> 1) << 2) | (j & 1);
+            const int jv = ((j >> 1) << 2) | ((j & 1) << 1);
+            kt = fmax(kt, fabs(f[jt] - f[4 | jt]));
+            ku = fmax(ku, fabs(f[ju] - f[2 | ju]));
+            kv = fmax(kv, fabs(f[jv] - f[1 | jv]));
+        }
+    }
+    kappa[0] = 3.0 * kt;
+    kappa[1] = 3.0 * ku;
+    kappa[2] = 3.0 * kv;
+}
+
 // Children of a non-terminal colliding box on the split axis; c1 may be
 // rejected by the prism test of vertex-face queries.
-__device__ __forceinline__ void children(const Query& Q, const State& S, const LevelInfo& L,
+__device__ __forceinline__ void children(int kind, const State& S, const LevelInfo& L,
                                          uint64_t bt, uint64_t bu, uint64_t bv, uint64_t c[2][3],
                                          bool ok[2]) {
     int d[3] = {S.d[0], S.d[1], S.d[2]};
@@ -243,13 +320,32 @@ __device__ __forceinline__ void children(const Query& Q, const State& S, const L
     for (int b = 0; b < 2; ++b) {
         c[b][0] = bt; c[b][1] = bu; c[b][2] = bv;
         c[b][L.axis] = 2 * c[b][L.axis] + (uint64_t)b;
-        ok[b] = (Q.kind == kEE) || vf_admit(c[b][1], d[1], c[b][2], d[2]);
+        ok[b] = (kind == kEE) || vf_admit(c[b][1], d[1], c[b][2], d[2]);
     }
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Values that are equal in every lane (LDS broadcasts, butterfly reductions)
+// made provably wave-uniform, so that they live in scalar registers and the
+// branches on them are scalar branches.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return (uint64_t)uni32((uint32_t)x) | ((uint64_t)uni32((uint32_t)(x >> 32)) << 32);
+}
+__device__ __forceinline__ int64_t uni64s(int64_t x) { return (int64_t)uni64((uint64_t)x); }
+__device__ __forceinline__ double unif64(double x) {
+    return __longlong_as_double((long long)uni64((uint64_t)__double_as_longlong(x)));
+}
+__device__ __forceinline__ void acc_uniform(Acc& A) {
+    A.ft = uni64(A.ft); A.fu = uni64(A.fu); A.fv = uni64(A.fv); A.fflags = uni32(A.fflags);
+    A.mt = uni64(A.mt); A.mu = uni64(A.mu); A.mv = uni64(A.mv); A.mhave = uni32(A.mhave);
+    A.tm = uni64(A.tm); A.thave = uni32(A.thave);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,6 +411,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
     uint32_t idx = 0, next_cnt = 0;
     int cur = 0;
     uint64_t nchk[2] = {0, 0};
+    uint64_t iters = 0;
 
     while (true) {
         if (PERSISTENT && !exhausted) {
@@ -325,7 +422,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 unsigned long long base = 0;
                 if (lane == leader)
                     base = atomicAdd(&a.counters[kCntCursor], (unsigned long long)__popcll(m));
-                base = __shfl(base, leader);
+                base = uni64(__shfl(base, leader));
                 if (need) {
                     const uint64_t r = base + __popcll(m & lanemask_lt());
                     if (r < (uint64_t)a.n) {
@@ -337,6 +434,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             }
         }
         if (__ballot(q >= 0) == 0) break;
+        iters += 1;
         if (q >= 0 && fresh) {
             fresh = false;
             bool valid;
@@ -355,9 +453,8 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 next_cnt = 0;
                 cur = 0;
                 acc_init(A);
-                L.wt = L.wu = L.wv = 1.0;
-                L.axis = 0;
-                L.dcap = false;
+                Q.kappa[0] = Q.kappa[1] = Q.kappa[2] = 0.0;  // set by the level-0 check
+                L = level_info(Q.kappa, S.d);
             }
         }
         if (q < 0) continue;
@@ -379,7 +476,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             if (!term) {
                 uint64_t ch[2][3];
                 bool ok[2];
-                children(Q, S, L, bt, bu, bv, ch, ok);
+                children(Q.kind, S, L, bt, bu, bv, ch, ok);
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     if (!ok[b]) continue;
@@ -397,7 +494,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
 
         // ---- end of the level: replay Alg. 2's decisions
         uint64_t rf = 0, rm = 0;
-        if (!root && need_rank(A, S, Q, L)) {
+        if (!root && need_rank(A, S, Q.literal, Q.max_iter, L)) {
             for (uint32_t i = 0; i < S.cnt; ++i) {
                 const uint64_t kt = ar[arena_idx(K, cur, i, 0)];
                 const uint64_t ku = ar[arena_idx(K, cur, i, 1)];
@@ -406,7 +503,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 rm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
             }
         }
-        const Outcome O = decide(A, S, Q, L, rf, rm);
+        const Outcome O = decide(A, S, Q.literal, Q.max_iter, L, rf, rm);
         if (O.finish) {
             write_result(a, q, O);
             q = -1;
@@ -417,7 +514,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
         const bool overflow = next_cnt > (uint32_t)K;
         bool promote = overflow;
         if (!overflow) {
-            advance(S, A, Q, L, next_cnt);
+            advance(S, A, Q.literal, L, next_cnt);
             cur ^= 1;
             idx = 0;
             next_cnt = 0;
@@ -452,7 +549,8 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             // else: budget hand-off without a free record; keep solving here
         }
     }
-    // per-wave check counters
+    // per-wave check and lane-slot counters
+    if (lane == 0 && iters) atomicAdd(&a.counters[kCntSlots + 0], (unsigned long long)iters * 64ull);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         unsigned long long v = nchk[k];
@@ -489,18 +587,170 @@ __device__ __forceinline__ void wave_reduce_acc(Acc& A) {
 
 template <int W>
 struct GroupShared {
+    double Xs[24];  // the query's coordinates, Xs[c*8 + k]
+    double Es[3];   // eps per axis
     Acc acc[W];
     unsigned long long sum[W][2];
     unsigned long long next_cnt;
     int64_t rec;
 };
 
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_group(BatchArgs a, GroupCfg g) {
+// The level loop of one query, run by the whole block.
+template <int W, int KIND>
+__device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
+                                            uint64_t* base, const Record& h, const double kappa[3],
+                                            double delta, double min_sep, int64_t max_iter,
+                                            bool literal, uint64_t& nchk, uint64_t& slots) {
     constexpr int T = 64 * W;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
+    const int64_t cap = g.capacity;
+    State S;
+    S.N = h.N; S.tpend = h.tpend; S.wpend = h.wpend; S.level = h.level;
+    S.d[0] = h.d[0]; S.d[1] = h.d[1]; S.d[2] = h.d[2]; S.cnt = h.cnt;
+    int cur = 0;
+    while (true) {
+        const LevelInfo L = level_info(kappa, S.d);
+        const uint64_t* ct = base + cur * 3 * cap;
+        uint64_t* nt = base + (cur ^ 1) * 3 * cap;
+        Acc A;
+        acc_init(A);
+        unsigned long long next_w = 0;  // W == 1: running size of the next level
+        if (W > 1) {
+            if (tid == 0) sh.next_cnt = 0;
+            __syncthreads();
+        }
+        const int64_t cnt = S.cnt;
+        const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
+        // software pipelining: the next chunk's boxes load while this one computes
+        uint64_t pt = 0, pu = 0, pv = 0;
+        if (tid < cnt) { pt = ct[tid]; pu = ct[cap + tid]; pv = ct[2 * cap + tid]; }
+        for (int64_t b0 = 0; b0 < cnt; b0 += T) {
+            const int64_t i = b0 + tid;
+            const bool act = i < cnt;
+            const uint64_t bt = pt, bu = pu, bv = pv;
+            const int64_t inx = i + T;
+            if (inx < cnt) { pt = ct[inx]; pu = ct[cap + inx]; pv = ct[2 * cap + inx]; }
+            bool e0 = false, e1 = false;
+            uint64_t ch[2][3];
+            if (act) {
+                const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
+                const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
+                const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
+                const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, t0, t0 + L.wt, u0, u0 + L.wu,
+                                                          v0, v0 + L.wv, min_sep, delta);
+                if (R.collide) {
+                    const bool term = R.small || L.dcap;
+                    acc_add(A, bt, bu, bv, term, R.small, cap_level);
+                    if (!term) {
+                        bool ok[2];
+                        children(KIND, S, L, bt, bu, bv, ch, ok);
+                        e0 = ok[0];
+                        e1 = ok[1];
+                    }
+                }
+            }
+            const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
+            const unsigned long long tot = __popcll(m0) + __popcll(m1);
+            unsigned long long wbase;
+            if (W == 1) {
+                wbase = next_w;
+                next_w += tot;
+            } else {
+                unsigned long long t = 0;
+                if (lane == 0 && tot) t = atomicAdd(&sh.next_cnt, tot);
+                wbase = uni64(__shfl(t, 0));
+            }
+            const uint64_t lt = lanemask_lt();
+            const int64_t p = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
+            if (e0 && p < cap) {
+                nt[p] = ch[0][0]; nt[cap + p] = ch[0][1]; nt[2 * cap + p] = ch[0][2];
+            }
+            const int64_t p1 = p + (e0 ? 1 : 0);
+            if (e1 && p1 < cap) {
+                nt[p1] = ch[1][0]; nt[cap + p1] = ch[1][1]; nt[2 * cap + p1] = ch[1][2];
+            }
+        }
+        if (tid == 0) {
+            nchk += (uint64_t)cnt;
+            slots += (uint64_t)((cnt + T - 1) / T) * T;
+        }
+        wave_reduce_acc(A);
+        uint64_t next_cnt;
+        if (W > 1) {
+            if (lane == 0) sh.acc[wid] = A;
+            __syncthreads();
+            A = sh.acc[0];
+            for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
+            next_cnt = uni64(sh.next_cnt);
+            __syncthreads();
+        } else {
+            next_cnt = next_w;
+        }
+        acc_uniform(A);
+        uint64_t rf = 0, rm = 0;
+        if (need_rank(A, S, literal, max_iter, L)) {
+            unsigned long long sf = 0, sm = 0;
+            for (int64_t i = tid; i < cnt; i += T) {
+                const uint64_t kt = ct[i], ku = ct[cap + i], kv = ct[2 * cap + i];
+                sf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
+                sm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                sf += __shfl_xor(sf, off);
+                sm += __shfl_xor(sm, off);
+            }
+            if (W > 1) {
+                if (lane == 0) { sh.sum[wid][0] = sf; sh.sum[wid][1] = sm; }
+                __syncthreads();
+                sf = 0; sm = 0;
+                for (int w = 0; w < W; ++w) { sf += sh.sum[w][0]; sm += sh.sum[w][1]; }
+                __syncthreads();
+            }
+            rf = uni64(sf);
+            rm = uni64(sm);
+        }
+        const Outcome O = decide(A, S, literal, max_iter, L, rf, rm);
+        if (O.finish) {
+            if (tid == 0) write_result(a, h.q, O);
+            return;
+        }
+        if (next_cnt > (uint64_t)cap) {
+            // the next level does not fit: restart the query in the next engine
+            if (tid == 0) {
+                bool placed = false;
+                if (g.out_records) {
+                    const unsigned long long o = atomicAdd(&a.counters[g.out_count_idx], 1ull);
+                    if ((int64_t)o < g.out_record_cap) {
+                        uint64_t* orec = g.out_records + (int64_t)o * g.out_record_words;
+                        Record nh;
+                        nh.q = h.q; nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
+                        nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.pad = 0;
+                        *reinterpret_cast<Record*>(orec) = nh;
+                        const int64_t ok = (g.out_record_words - kRecordHeaderWords) / 3;
+                        orec[kRecordHeaderWords] = 0;
+                        orec[kRecordHeaderWords + ok] = 0;
+                        orec[kRecordHeaderWords + 2 * ok] = 0;
+                        placed = true;
+                    }
+                }
+                if (!placed) atomicAdd(&a.counters[kCntError], 1ull);
+            }
+            return;
+        }
+        advance(S, A, literal, L, (uint32_t)next_cnt);
+        cur ^= 1;
+        __syncthreads();
+    }
+}
+
+// OCC: minimum resident waves per SIMD the register allocation must allow.
+template <int W, int OCC>
+__global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) {
+    constexpr int T = 64 * W;
+    const int tid = threadIdx.x;
     __shared__ GroupShared<W> sh;
     const int64_t cap = g.capacity;
     uint64_t* base = g.arena + (int64_t)blockIdx.x * (6 * cap);
@@ -508,173 +758,66 @@ __global__ __launch_bounds__(64 * W) void k_group(BatchArgs a, GroupCfg g) {
     if (in_count > g.in_record_cap) in_count = g.in_record_cap;
     const int64_t in_k = (g.in_record_words - kRecordHeaderWords) / 3;
     uint64_t nchk[2] = {0, 0};
+    uint64_t slots = 0;
+    const bool literal = (a.flags & kFlagLiteral) != 0;
 
     while (true) {
         if (tid == 0) sh.rec = (int64_t)atomicAdd(&a.counters[g.in_take_idx], 1ull);
         __syncthreads();
-        const int64_t r = sh.rec;
-        __syncthreads();
+        const int64_t r = uni64s(sh.rec);
         if (r >= in_count) break;
         const uint64_t* rec = g.in_records + r * g.in_record_words;
         const Record h = *reinterpret_cast<const Record*>(rec);
-        Query Q;
-        bool valid;
-        load_query(a, h.q, Q, valid);
-        {
-            LevelInfo L0;
-            L0.wt = L0.wu = L0.wv = 1.0;
-            L0.axis = 0;
-            L0.dcap = false;
-            check_any(Q, L0, 0, 0, 0, true, Q.kappa);
+        const int64_t q = h.q;
+        const int kind = a.kind ? (int)a.kind[q] : (int)a.default_kind;
+        const double delta = a.delta_q ? a.delta_q[q] : a.delta;
+        const int64_t max_iter = a.max_iter_q ? a.max_iter_q[q] : a.max_iter;
+        const double min_sep = a.min_sep_q ? a.min_sep_q[q] : a.min_sep;
+        if (tid < 24) {
+            const int c = tid % 3, k = tid / 3;
+            sh.Xs[c * 8 + k] = a.pos[(int64_t)tid * a.n + q];
         }
-        State S;
-        S.N = h.N; S.tpend = h.tpend; S.wpend = h.wpend; S.level = h.level;
-        S.d[0] = h.d[0]; S.d[1] = h.d[1]; S.d[2] = h.d[2]; S.cnt = h.cnt;
         const uint64_t* rb = rec + kRecordHeaderWords;
-        for (int64_t i = tid; i < (int64_t)S.cnt; i += T) {
+        for (int64_t i = tid; i < (int64_t)h.cnt; i += T) {
             base[i] = rb[i];
             base[cap + i] = rb[in_k + i];
             base[2 * cap + i] = rb[2 * in_k + i];
         }
         __syncthreads();
-        int cur = 0;
-        while (true) {
-            const LevelInfo L = level_info(Q.kappa, S.d);
-            const uint64_t* ct = base + cur * 3 * cap;
-            uint64_t* nt = base + (cur ^ 1) * 3 * cap;
-            Acc A;
-            acc_init(A);
-            unsigned long long next_w = 0;  // W == 1: running count of the next level
-            if (W > 1) {
-                if (tid == 0) sh.next_cnt = 0;
-                __syncthreads();
-            }
-            for (int64_t b0 = 0; b0 < (int64_t)S.cnt; b0 += T) {
-                const int64_t i = b0 + tid;
-                const bool act = i < (int64_t)S.cnt;
-                bool e0 = false, e1 = false;
-                uint64_t ch[2][3];
-                if (act) {
-                    const uint64_t bt = ct[i], bu = ct[cap + i], bv = ct[2 * cap + i];
-                    double dummy[3];
-                    const CheckResult R = check_any(Q, L, bt, bu, bv, false, dummy);
-                    if (R.collide) {
-                        const bool term = R.small || L.dcap;
-                        acc_add(A, bt, bu, bv, term, R.small);
-                        if (!term) {
-                            bool ok[2];
-                            children(Q, S, L, bt, bu, bv, ch, ok);
-                            e0 = ok[0];
-                            e1 = ok[1];
-                        }
-                    }
-                }
-                const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
-                const unsigned long long tot = __popcll(m0) + __popcll(m1);
-                unsigned long long wbase;
-                if (W == 1) {
-                    wbase = next_w;
-                    next_w += tot;
-                } else {
-                    unsigned long long t = 0;
-                    if (lane == 0 && tot) t = atomicAdd(&sh.next_cnt, tot);
-                    wbase = __shfl(t, 0);
-                }
-                const uint64_t lt = lanemask_lt();
-                const int64_t p = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
-                if (e0 && p < cap) {
-                    nt[p] = ch[0][0]; nt[cap + p] = ch[0][1]; nt[2 * cap + p] = ch[0][2];
-                }
-                const int64_t p1 = p + (e0 ? 1 : 0);
-                if (e1 && p1 < cap) {
-                    nt[p1] = ch[1][0]; nt[cap + p1] = ch[1][1]; nt[2 * cap + p1] = ch[1][2];
-                }
-            }
-            const uint64_t cnt_here = S.cnt;
-            wave_reduce_acc(A);
-            uint64_t next_cnt;
-            if (W > 1) {
-                if (lane == 0) sh.acc[wid] = A;
-                __syncthreads();
-                A = sh.acc[0];
-                for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
-                next_cnt = sh.next_cnt;
-                __syncthreads();
-            } else {
-                next_cnt = next_w;
-            }
-            uint64_t rf = 0, rm = 0;
-            if (need_rank(A, S, Q, L)) {
-                unsigned long long sf = 0, sm = 0;
-                for (int64_t i = tid; i < (int64_t)S.cnt; i += T) {
-                    const uint64_t kt = ct[i], ku = ct[cap + i], kv = ct[2 * cap + i];
-                    sf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
-                    sm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
-                }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    sf += __shfl_xor(sf, off);
-                    sm += __shfl_xor(sm, off);
-                }
-                if (W > 1) {
-                    if (lane == 0) { sh.sum[wid][0] = sf; sh.sum[wid][1] = sm; }
-                    __syncthreads();
-                    sf = 0; sm = 0;
-                    for (int w = 0; w < W; ++w) { sf += sh.sum[w][0]; sm += sh.sum[w][1]; }
-                    __syncthreads();
-                }
-                rf = sf;
-                rm = sm;
-            }
-            if (tid == 0) nchk[Q.kind] += cnt_here;
-            const Outcome O = decide(A, S, Q, L, rf, rm);
-            if (O.finish) {
-                if (tid == 0) write_result(a, h.q, O);
-                break;
-            }
-            if (next_cnt > (uint64_t)cap) {
-                // the next level does not fit: restart the query in the next engine
-                if (tid == 0) {
-                    if (g.out_records) {
-                        const unsigned long long o = atomicAdd(&a.counters[g.out_count_idx], 1ull);
-                        if ((int64_t)o < g.out_record_cap) {
-                            uint64_t* orec = g.out_records + (int64_t)o * g.out_record_words;
-                            Record nh;
-                            nh.q = h.q; nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
-                            nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.pad = 0;
-                            *reinterpret_cast<Record*>(orec) = nh;
-                            const int64_t ok = (g.out_record_words - kRecordHeaderWords) / 3;
-                            orec[kRecordHeaderWords] = 0;
-                            orec[kRecordHeaderWords + ok] = 0;
-                            orec[kRecordHeaderWords + 2 * ok] = 0;
-                        } else {
-                            atomicAdd(&a.counters[kCntError], 1ull);
-                        }
-                    } else {
-                        atomicAdd(&a.counters[kCntError], 1ull);
-                    }
-                }
-                break;
-            }
-            advance(S, A, Q, L, (uint32_t)next_cnt);
-            cur ^= 1;
-            __syncthreads();
+        if (tid < 3) {
+            // gamma_c and eps_c (Sec. 4.2); min_sep > 0 selects the Sec. 5.1 constants
+            const double K = filter_constant(kind, min_sep);
+            double gm = 1.0;
+            for (int k = 0; k < 8; ++k) gm = fmax(gm, fabs(sh.Xs[tid * 8 + k]));
+            sh.Es[tid] = ((K * gm) * gm) * gm;
         }
+        double kappa[3];
+        if (kind == kEE) kappa_lds<kEE>(sh.Xs, kappa);
+        else kappa_lds<kVF>(sh.Xs, kappa);
+        __syncthreads();
+        if (kind == kEE)
+            group_query<W, kEE>(a, g, sh, base, h, kappa, delta, min_sep, max_iter, literal, nchk[1], slots);
+        else
+            group_query<W, kVF>(a, g, sh, base, h, kappa, delta, min_sep, max_iter, literal, nchk[0], slots);
         __syncthreads();
     }
     if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (nchk[k]) atomicAdd(&a.counters[kCntChecks + 2 * g.tier + k], (unsigned long long)nchk[k]);
+        if (slots) atomicAdd(&a.counters[kCntSlots + g.tier], (unsigned long long)slots);
     }
 }
 
 // Explicit instantiations used by the runtime.
 template __global__ void k_lane<false>(BatchArgs, LaneCfg);
 template __global__ void k_lane<true>(BatchArgs, LaneCfg);
-template __global__ void k_group<1>(BatchArgs, GroupCfg);
-template __global__ void k_group<2>(BatchArgs, GroupCfg);
-template __global__ void k_group<4>(BatchArgs, GroupCfg);
-template __global__ void k_group<8>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 1>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 2>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 3>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 4>(BatchArgs, GroupCfg);
+template __global__ void k_group<2, 1>(BatchArgs, GroupCfg);
+template __global__ void k_group<4, 1>(BatchArgs, GroupCfg);
+template __global__ void k_group<8, 1>(BatchArgs, GroupCfg);
 
 }  // namespace ccd

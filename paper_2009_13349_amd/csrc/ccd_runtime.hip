@@ -23,7 +23,7 @@
 namespace ccd {
 template <bool P>
 __global__ void k_lane(BatchArgs a, LaneCfg c);
-template <int W>
+template <int W, int OCC>
 __global__ void k_group(BatchArgs a, GroupCfg g);
 __global__ void k_partition(BatchArgs a, int64_t* order);
 __global__ void k_reset(unsigned long long* counters);
@@ -96,10 +96,10 @@ void default_tuning(ccd_tuning& t, int num_cu) {
     t.lane_capacity = 32;
     t.lane_budget = 256;
     t.group_waves = 1;
-    t.group_count = num_cu * 4;
+    t.group_count = num_cu * 12;
     t.group_capacity = 1 << 16;
     t.block_count = num_cu;
-    t.reserved = 0;
+    t.group_occupancy = 3;
 }
 
 void clamp_tuning(ccd_tuning& t) {
@@ -113,6 +113,7 @@ void clamp_tuning(ccd_tuning& t) {
     t.group_count = std::min(1 << 16, std::max(1, t.group_count));
     t.group_capacity = std::min<int64_t>(int64_t(1) << 28, std::max<int64_t>(256, t.group_capacity));
     t.block_count = std::min(1 << 12, std::max(1, t.block_count));
+    t.group_occupancy = std::min(4, std::max(1, t.group_occupancy));
 }
 
 bool params_ok(const ccd_params& p) {
@@ -178,12 +179,13 @@ int make_plan(ccd_context* ctx, int64_t n, int64_t max_iter_max, bool persistent
     const size_t per_block = (size_t)6 * P.block_cap * 8;
     if (fixed + per_group + per_block > ctx->budget) return CCD_ENOMEM;
     size_t left = ctx->budget - fixed;
-    // give the block engine at most half of what is left, the group engine the rest
-    size_t blocks_fit = std::max<size_t>(1, (left / 2) / per_block);
-    P.block_count = (int)std::min<size_t>(P.block_count, blocks_fit);
-    left -= (size_t)P.block_count * per_block;
-    size_t groups_fit = std::max<size_t>(1, left / per_group);
+    // the group engine carries the bulk of the work: it gets up to 3/4 of what is
+    // left after one block arena; the block engine (rarely used) gets the rest
+    size_t groups_fit = std::max<size_t>(1, ((left - per_block) / 4 * 3) / per_group);
     P.group_count = (int)std::min<size_t>(P.group_count, groups_fit);
+    left -= (size_t)P.group_count * per_group;
+    size_t blocks_fit = std::max<size_t>(1, left / per_block);
+    P.block_count = (int)std::min<size_t>(P.block_count, blocks_fit);
     return CCD_OK;
 }
 
@@ -240,16 +242,28 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
     g.tier = 1;
     switch (ctx->tune.group_waves) {
         case 8:
-            hipLaunchKernelGGL(k_group<8>, dim3(P.group_count), dim3(512), 0, s, a, g);
+            hipLaunchKernelGGL((k_group<8, 1>), dim3(P.group_count), dim3(512), 0, s, a, g);
             break;
         case 2:
-            hipLaunchKernelGGL(k_group<2>, dim3(P.group_count), dim3(128), 0, s, a, g);
+            hipLaunchKernelGGL((k_group<2, 1>), dim3(P.group_count), dim3(128), 0, s, a, g);
             break;
         case 4:
-            hipLaunchKernelGGL(k_group<4>, dim3(P.group_count), dim3(256), 0, s, a, g);
+            hipLaunchKernelGGL((k_group<4, 1>), dim3(P.group_count), dim3(256), 0, s, a, g);
             break;
         default:
-            hipLaunchKernelGGL(k_group<1>, dim3(P.group_count), dim3(64), 0, s, a, g);
+            switch (ctx->tune.group_occupancy) {
+                case 4:
+                    hipLaunchKernelGGL((k_group<1, 4>), dim3(P.group_count), dim3(64), 0, s, a, g);
+                    break;
+                case 3:
+                    hipLaunchKernelGGL((k_group<1, 3>), dim3(P.group_count), dim3(64), 0, s, a, g);
+                    break;
+                case 2:
+                    hipLaunchKernelGGL((k_group<1, 2>), dim3(P.group_count), dim3(64), 0, s, a, g);
+                    break;
+                default:
+                    hipLaunchKernelGGL((k_group<1, 1>), dim3(P.group_count), dim3(64), 0, s, a, g);
+            }
     }
     if (timed) (void)hipEventRecord(ctx->ev[3], s);
 
@@ -266,7 +280,7 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
     b.out_record_cap = 0;
     b.out_count_idx = 0;
     b.tier = 2;
-    hipLaunchKernelGGL(k_group<8>, dim3(P.block_count), dim3(512), 0, s, a, b);
+    hipLaunchKernelGGL((k_group<8, 1>), dim3(P.block_count), dim3(512), 0, s, a, b);
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
     ctx->last_timed = timed;
     ctx->last_valid = true;
@@ -399,6 +413,7 @@ int ccd_context_set_tuning(ccd_context* c, const ccd_tuning* t) {
     if (t->group_count) n.group_count = t->group_count;
     if (t->group_capacity) n.group_capacity = t->group_capacity;
     if (t->block_count) n.block_count = t->block_count;
+    if (t->group_occupancy) n.group_occupancy = t->group_occupancy;
     clamp_tuning(n);
     c->tune = n;
     return CCD_OK;
@@ -423,6 +438,7 @@ int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
         for (int k = 0; k < 2; ++k) out->checks[t][k] = h[kCntChecks + 2 * t + k];
     out->promoted[0] = h[kCntRecA];
     out->promoted[1] = h[kCntRecB];
+    for (int t = 0; t < 3; ++t) out->lane_slots[t] = h[kCntSlots + t];
     if (c->last_timed)
         for (int i = 0; i < 4; ++i) (void)hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]);
     if (h[kCntError]) return CCD_ENOMEM;

@@ -67,7 +67,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ccd.Tuning) == 40
     assert ctypes.sizeof(ccd.BatchDesc) == 104
     assert ctypes.sizeof(ccd.ResultSoA) == 40
-    assert ctypes.sizeof(ccd.Stats) == 80
+    assert ctypes.sizeof(ccd.Stats) == 104
 
 
 def test_null_arguments_rejected_without_gpu(lib):
