@@ -85,6 +85,31 @@ def roofline(stats, kind_counts):
     }
 
 
+def kernel_symbol(tier: int, tuning: dict) -> str:
+    if tier == 0:
+        return "ccd::k_lane<true>"
+    if tier == 2:
+        return "ccd::k_group<8, 1>"
+    gw = tuning["group_waves"]
+    return f"ccd::k_group<{gw}, {tuning['group_occupancy'] if gw == 1 else 1}>"
+
+
+def hbm_traffic(symbol: str):
+    """Per-launch HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded
+    under profiles/ for these exact kernel sources, else None."""
+    from paper_2009_13349_amd.rocprof_summary import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = rec["kernels"].get(symbol)
+    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline(w, seconds: float):
     """The oracle (single thread, as it stands) on a seeded random sample of
     the same workload, scaled to queries/s."""
@@ -163,6 +188,12 @@ def main():
                  "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
                                    for i in range(4)}}
     rl = roofline(stats_p, kind_counts)
+    tier = KERNELS.index(rl["kernel"]) - 1
+    rl["symbol"] = kernel_symbol(tier, ctx.tuning())
+    tb = hbm_traffic(rl["symbol"])
+    rl["traffic"] = round(tb) if tb else None
+    rl["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    rl["hbm_gbps"] = round(tb / (rl["avg_launch_ms"] * 1e-3) / 1e9, 1) if tb else None
     checks_total = int(sum(sum(c) for c in stats_p[-1]["checks"]))
     alg_flops = alg_checks[0] * FLOP_PER_CHECK[0] + alg_checks[1] * FLOP_PER_CHECK[1]
     path_alg_tflops = alg_flops / (t_p / args.steps) / 1e12
