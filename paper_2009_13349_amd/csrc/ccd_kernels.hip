@@ -595,7 +595,206 @@ struct GroupShared {
     int64_t rec;
 };
 
-// The level loop of one query, run by the whole block.
+// ---------------------------------------------------------------------------
+// Frontier encodings of the group engine.  A level whose total bisection depth
+// D = dt + du + dv is at most 64 stores each box as one u64 key
+//   key = (it << (du + dv)) | (iu << dv) | iv,
+// whose numeric order is the lexicographic (t, u, v) order of Alg. 2; deeper
+// levels store the three indices in three arrays.
+
+__device__ __forceinline__ uint64_t shl64(uint64_t x, int s) { return s >= 64 ? 0ull : x << s; }
+__device__ __forceinline__ uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; }
+__device__ __forceinline__ uint64_t mask64(int d) { return d >= 64 ? ~0ull : ((1ull << d) - 1ull); }
+
+struct KeyCodec {
+    int st, su;        // shifts of the t and u fields
+    uint64_t mu, mv;   // masks of the u and v fields
+    __device__ __forceinline__ void init(int du, int dv) {
+        st = du + dv;
+        su = dv;
+        mu = mask64(du);
+        mv = mask64(dv);
+    }
+    __device__ __forceinline__ uint64_t encode(uint64_t t, uint64_t u, uint64_t v) const {
+        return shl64(t, st) | shl64(u, su) | v;
+    }
+    __device__ __forceinline__ void decode(uint64_t k, uint64_t& t, uint64_t& u, uint64_t& v) const {
+        t = shr64(k, st);
+        u = shr64(k, su) & mu;
+        v = k & mv;
+    }
+};
+
+// Accumulation with single-word keys (packed levels).
+__device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt, bool term,
+                                               bool small, bool track_max) {
+    if (!(A.fflags & 1u) || key < A.ft) {
+        A.ft = key;
+        A.fu = 0;
+        A.fv = 0;
+        A.fflags = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
+    }
+    if (track_max && (!A.mhave || A.mt < key)) {
+        A.mt = key;
+        A.mu = 0;
+        A.mv = 0;
+        A.mhave = 1;
+    }
+    if (term && (!A.thave || bt < A.tm)) {
+        A.tm = bt;
+        A.thave = 1;
+    }
+}
+
+// One level of one query, run by the whole block: check every box, accumulate,
+// and write the admitted children of non-terminal colliding boxes.  PR / PW:
+// the level / the next level is stored packed.  Returns the block-reduced,
+// wave-uniform accumulator with keys as (t, u, v) indices, and the next
+// level's size.
+template <int W, int KIND, bool PR, bool PW>
+__device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
+                                           int64_t cap, const State& S, const LevelInfo& L,
+                                           double min_sep, double delta, bool cap_level,
+                                           Acc& A, uint64_t& next_cnt) {
+    constexpr int T = 64 * W;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    KeyCodec kc, cc;
+    kc.init(S.d[1], S.d[2]);
+    int cd[3] = {S.d[0], S.d[1], S.d[2]};
+    cd[L.axis] += 1;
+    cc.init(cd[1], cd[2]);
+    acc_init(A);
+    unsigned long long next_w = 0;  // W == 1: running size of the next level
+    if (W > 1) {
+        if (tid == 0) sh.next_cnt = 0;
+        __syncthreads();
+    }
+    const int64_t cnt = S.cnt;
+    // software pipelining: the next chunk's boxes load while this one computes
+    uint64_t p0 = 0, p1 = 0, p2 = 0;
+    if (tid < cnt) {
+        p0 = ct[tid];
+        if (!PR) { p1 = ct[cap + tid]; p2 = ct[2 * cap + tid]; }
+    }
+    for (int64_t b0 = 0; b0 < cnt; b0 += T) {
+        const int64_t i = b0 + tid;
+        const bool act = i < cnt;
+        uint64_t bt, bu, bv;
+        const uint64_t key = p0;
+        if (PR) kc.decode(key, bt, bu, bv);
+        else { bt = p0; bu = p1; bv = p2; }
+        const int64_t inx = i + T;
+        if (inx < cnt) {
+            p0 = ct[inx];
+            if (!PR) { p1 = ct[cap + inx]; p2 = ct[2 * cap + inx]; }
+        }
+        bool e0 = false, e1 = false;
+        uint64_t ch[2][3];
+        if (act) {
+            const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
+            const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
+            const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
+            const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, t0, t0 + L.wt, u0, u0 + L.wu,
+                                                      v0, v0 + L.wv, min_sep, delta);
+            if (R.collide) {
+                const bool term = R.small || L.dcap;
+                if (PR) acc_add_packed(A, key, bt, term, R.small, cap_level);
+                else acc_add(A, bt, bu, bv, term, R.small, cap_level);
+                if (!term) {
+                    bool ok[2];
+                    children(KIND, S, L, bt, bu, bv, ch, ok);
+                    e0 = ok[0];
+                    e1 = ok[1];
+                }
+            }
+        }
+        const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
+        const unsigned long long tot = __popcll(m0) + __popcll(m1);
+        unsigned long long wbase;
+        if (W == 1) {
+            wbase = next_w;
+            next_w += tot;
+        } else {
+            unsigned long long t = 0;
+            if (lane == 0 && tot) t = atomicAdd(&sh.next_cnt, tot);
+            wbase = uni64(__shfl(t, 0));
+        }
+        const uint64_t lt = lanemask_lt();
+        const int64_t q0 = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
+        const int64_t q1 = q0 + (e0 ? 1 : 0);
+        if (PW) {
+            if (e0 && q0 < cap) nt[q0] = cc.encode(ch[0][0], ch[0][1], ch[0][2]);
+            if (e1 && q1 < cap) nt[q1] = cc.encode(ch[1][0], ch[1][1], ch[1][2]);
+        } else {
+            if (e0 && q0 < cap) { nt[q0] = ch[0][0]; nt[cap + q0] = ch[0][1]; nt[2 * cap + q0] = ch[0][2]; }
+            if (e1 && q1 < cap) { nt[q1] = ch[1][0]; nt[cap + q1] = ch[1][1]; nt[2 * cap + q1] = ch[1][2]; }
+        }
+    }
+    wave_reduce_acc(A);
+    if (W > 1) {
+        if (lane == 0) sh.acc[wid] = A;
+        __syncthreads();
+        A = sh.acc[0];
+        for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
+        next_cnt = uni64(sh.next_cnt);
+        __syncthreads();
+    } else {
+        next_cnt = next_w;
+    }
+    acc_uniform(A);
+    if (PR) {
+        uint64_t t, u, v;
+        if (A.fflags & 1u) { kc.decode(A.ft, t, u, v); A.ft = t; A.fu = u; A.fv = v; }
+        if (A.mhave) { kc.decode(A.mt, t, u, v); A.mt = t; A.mu = u; A.mv = v; }
+    }
+}
+
+// Number of boxes of the level below f and below m (keys as (t, u, v)).
+template <int W, bool PR>
+__device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct, int64_t cap,
+                                          const State& S, const Acc& A, uint64_t& rf, uint64_t& rm) {
+    constexpr int T = 64 * W;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    KeyCodec kc;
+    kc.init(S.d[1], S.d[2]);
+    const uint64_t fk = kc.encode(A.ft, A.fu, A.fv);
+    const uint64_t mk = kc.encode(A.mt, A.mu, A.mv);
+    unsigned long long sf = 0, sm = 0;
+    for (int64_t i = tid; i < (int64_t)S.cnt; i += T) {
+        if (PR) {
+            const uint64_t k = ct[i];
+            sf += k < fk ? 1 : 0;
+            sm += k < mk ? 1 : 0;
+        } else {
+            const uint64_t kt = ct[i], ku = ct[cap + i], kv = ct[2 * cap + i];
+            sf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
+            sm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sf += __shfl_xor(sf, off);
+        sm += __shfl_xor(sm, off);
+    }
+    if (W > 1) {
+        if (lane == 0) { sh.sum[wid][0] = sf; sh.sum[wid][1] = sm; }
+        __syncthreads();
+        sf = 0; sm = 0;
+        for (int w = 0; w < W; ++w) { sf += sh.sum[w][0]; sm += sh.sum[w][1]; }
+        __syncthreads();
+    }
+    rf = uni64(sf);
+    rm = uni64(sm);
+}
+
+__device__ __forceinline__ int depth_sum(const int32_t d[3]) { return d[0] + d[1] + d[2]; }
+
+// The level loop of one query, run by the whole block.  The level's boxes are
+// in buffer 0 of the block's arena when it starts.
 template <int W, int KIND>
 __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
                                             uint64_t* base, const Record& h, const double kappa[3],
@@ -603,8 +802,6 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
                                             bool literal, uint64_t& nchk, uint64_t& slots) {
     constexpr int T = 64 * W;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
     const int64_t cap = g.capacity;
     State S;
     S.N = h.N; S.tpend = h.tpend; S.wpend = h.wpend; S.level = h.level;
@@ -614,103 +811,25 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
         const LevelInfo L = level_info(kappa, S.d);
         const uint64_t* ct = base + cur * 3 * cap;
         uint64_t* nt = base + (cur ^ 1) * 3 * cap;
-        Acc A;
-        acc_init(A);
-        unsigned long long next_w = 0;  // W == 1: running size of the next level
-        if (W > 1) {
-            if (tid == 0) sh.next_cnt = 0;
-            __syncthreads();
-        }
-        const int64_t cnt = S.cnt;
+        const bool pr = depth_sum(S.d) <= 64;
+        const bool pw = depth_sum(S.d) + 1 <= 64;
         const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
-        // software pipelining: the next chunk's boxes load while this one computes
-        uint64_t pt = 0, pu = 0, pv = 0;
-        if (tid < cnt) { pt = ct[tid]; pu = ct[cap + tid]; pv = ct[2 * cap + tid]; }
-        for (int64_t b0 = 0; b0 < cnt; b0 += T) {
-            const int64_t i = b0 + tid;
-            const bool act = i < cnt;
-            const uint64_t bt = pt, bu = pu, bv = pv;
-            const int64_t inx = i + T;
-            if (inx < cnt) { pt = ct[inx]; pu = ct[cap + inx]; pv = ct[2 * cap + inx]; }
-            bool e0 = false, e1 = false;
-            uint64_t ch[2][3];
-            if (act) {
-                const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
-                const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
-                const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
-                const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, t0, t0 + L.wt, u0, u0 + L.wu,
-                                                          v0, v0 + L.wv, min_sep, delta);
-                if (R.collide) {
-                    const bool term = R.small || L.dcap;
-                    acc_add(A, bt, bu, bv, term, R.small, cap_level);
-                    if (!term) {
-                        bool ok[2];
-                        children(KIND, S, L, bt, bu, bv, ch, ok);
-                        e0 = ok[0];
-                        e1 = ok[1];
-                    }
-                }
-            }
-            const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
-            const unsigned long long tot = __popcll(m0) + __popcll(m1);
-            unsigned long long wbase;
-            if (W == 1) {
-                wbase = next_w;
-                next_w += tot;
-            } else {
-                unsigned long long t = 0;
-                if (lane == 0 && tot) t = atomicAdd(&sh.next_cnt, tot);
-                wbase = uni64(__shfl(t, 0));
-            }
-            const uint64_t lt = lanemask_lt();
-            const int64_t p = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
-            if (e0 && p < cap) {
-                nt[p] = ch[0][0]; nt[cap + p] = ch[0][1]; nt[2 * cap + p] = ch[0][2];
-            }
-            const int64_t p1 = p + (e0 ? 1 : 0);
-            if (e1 && p1 < cap) {
-                nt[p1] = ch[1][0]; nt[cap + p1] = ch[1][1]; nt[2 * cap + p1] = ch[1][2];
-            }
-        }
-        if (tid == 0) {
-            nchk += (uint64_t)cnt;
-            slots += (uint64_t)((cnt + T - 1) / T) * T;
-        }
-        wave_reduce_acc(A);
+        Acc A;
         uint64_t next_cnt;
-        if (W > 1) {
-            if (lane == 0) sh.acc[wid] = A;
-            __syncthreads();
-            A = sh.acc[0];
-            for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
-            next_cnt = uni64(sh.next_cnt);
-            __syncthreads();
-        } else {
-            next_cnt = next_w;
+        if (pw)
+            level_pass<W, KIND, true, true>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+        else if (pr)
+            level_pass<W, KIND, true, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+        else
+            level_pass<W, KIND, false, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+        if (tid == 0) {
+            nchk += (uint64_t)S.cnt;
+            slots += (uint64_t)((S.cnt + T - 1) / T) * T;
         }
-        acc_uniform(A);
         uint64_t rf = 0, rm = 0;
         if (need_rank(A, S, literal, max_iter, L)) {
-            unsigned long long sf = 0, sm = 0;
-            for (int64_t i = tid; i < cnt; i += T) {
-                const uint64_t kt = ct[i], ku = ct[cap + i], kv = ct[2 * cap + i];
-                sf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
-                sm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                sf += __shfl_xor(sf, off);
-                sm += __shfl_xor(sm, off);
-            }
-            if (W > 1) {
-                if (lane == 0) { sh.sum[wid][0] = sf; sh.sum[wid][1] = sm; }
-                __syncthreads();
-                sf = 0; sm = 0;
-                for (int w = 0; w < W; ++w) { sf += sh.sum[w][0]; sm += sh.sum[w][1]; }
-                __syncthreads();
-            }
-            rf = uni64(sf);
-            rm = uni64(sm);
+            if (pr) rank_pass<W, true>(sh, ct, cap, S, A, rf, rm);
+            else rank_pass<W, false>(sh, ct, cap, S, A, rf, rm);
         }
         const Outcome O = decide(A, S, literal, max_iter, L, rf, rm);
         if (O.finish) {
@@ -778,10 +897,17 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
             sh.Xs[c * 8 + k] = a.pos[(int64_t)tid * a.n + q];
         }
         const uint64_t* rb = rec + kRecordHeaderWords;
-        for (int64_t i = tid; i < (int64_t)h.cnt; i += T) {
-            base[i] = rb[i];
-            base[cap + i] = rb[in_k + i];
-            base[2 * cap + i] = rb[2 * in_k + i];
+        if (depth_sum(h.d) <= 64) {
+            KeyCodec kc;
+            kc.init(h.d[1], h.d[2]);
+            for (int64_t i = tid; i < (int64_t)h.cnt; i += T)
+                base[i] = kc.encode(rb[i], rb[in_k + i], rb[2 * in_k + i]);
+        } else {
+            for (int64_t i = tid; i < (int64_t)h.cnt; i += T) {
+                base[i] = rb[i];
+                base[cap + i] = rb[in_k + i];
+                base[2 * cap + i] = rb[2 * in_k + i];
+            }
         }
         __syncthreads();
         if (tid < 3) {

@@ -265,3 +265,20 @@ def test_full_size_edge_edge_sampled(ctx, torch_dev):
     assert_same(got, ref, idx=idx, what="edge_edge_mixed_100k sample")
     # constructed crossings are always found
     assert got["hit"][w["cls"] == 1].all()
+
+
+@pytest.mark.parametrize("scale,delta", [(1.0, 1e-8), (64.0, 1e-7)])
+def test_deep_levels(ctx, torch_dev, scale, delta):
+    """Small delta / large coordinates drive the total bisection depth past 64,
+    so the group engine moves from one-word to three-word box keys mid-query;
+    a one-check lane budget sends every query there."""
+    w = W.concat([W.uniform_vf(300, seed=31), W.edge_edge_mixed(300, seed=32, degenerate_frac=0.0)])
+    w["pos"] = w["pos"] * scale
+    ref = run_oracle(w, delta=delta)
+    for tune in ({}, {"lane_budget": 1}, {"lane_budget": 1, "group_waves": 4}):
+        if tune:
+            ctx.set_tuning(**tune)
+        got = run_gpu(ctx, torch_dev, w, 0, delta=delta)
+        assert_same(got, ref, what=f"deep levels scale={scale} delta={delta} tuning={tune}")
+    r = oracle.solve(0, w["pos"][:, 1], delta)
+    assert sum(r.depth) > 64
