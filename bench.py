@@ -37,10 +37,10 @@ def make_workload(name: str, n: int | None):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup):
+def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup, timing=True):
     from paper_2009_13349_amd import ccd
     ctx.set_engine(engine)
-    ctx.enable_timing(True)
+    ctx.enable_timing(timing)
     out = None
     kw = dict(delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
     for _ in range(warmup):
@@ -52,7 +52,8 @@ def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         out = ctx.batch_device(pos, kind, out=out, **kw)
-        stats.append(ctx.last_stats())  # synchronises; reads the per-kernel HIP events
+        if timing:
+            stats.append(ctx.last_stats())  # synchronises; reads the per-kernel HIP events
         per_step.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -180,6 +181,10 @@ def main():
     nck = out.n_checks.to(torch.float64)
     alg_checks = [float((nck * (kind == k)).sum().item()) for k in (0, 1)]
     value = n * args.steps / t_p
+    # the same steps replaying the captured hipGraph (no per-kernel events)
+    t_g, _, _ = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps, 1,
+                           timing=False)
+    graph_counts = ctx.graph_counts()
     plain = None
     if not args.no_plain:
         t_b, stats_b, _ = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PLAIN, args.steps,
@@ -217,6 +222,9 @@ def main():
                    "min_sep": w["min_sep"], "engine": "persistent", "parallelism": "single GPU"},
         "plain_kernel": plain,
         "speedup_vs_plain": round(value / plain["value"], 3) if plain else None,
+        "graph_replay": {"value": round(n * args.steps / t_g, 1),
+                         "ms_per_step": round(1e3 * t_g / args.steps, 3),
+                         "graphs_built": graph_counts[0], "replays": graph_counts[1]},
         "hits": hits,
         "box_checks_per_step": checks_total,
         "sequential_checks_per_step": int(sum(alg_checks)),

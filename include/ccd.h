@@ -185,6 +185,16 @@ typedef struct ccd_result_soa {
 int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa* out,
               void* stream);
 
+/*
+ * The launch sequence of a batch is captured into a hipGraph and replayed while
+ * its parameters (pointers, sizes, tuning) are unchanged; a change rebuilds it.
+ * Enabled by default; disabling launches the kernels one by one, and so does
+ * per-kernel timing (ccd_context_enable_timing).  Results are the same either way.  graph_counts reports how many graphs were built and
+ * how many launches replayed an existing one.
+ */
+int ccd_context_enable_graphs(ccd_context* ctx, int enable);
+int ccd_context_graph_counts(ccd_context* ctx, uint64_t* builds, uint64_t* replays);
+
 /* Counters of the last ccd_batch on a context (host copy; synchronises). */
 typedef struct ccd_stats {
     uint64_t checks[3][2];   /* box checks executed by tier [lane, group, block] x kind [VF, EE] */

@@ -26,6 +26,7 @@ EXPORTED = [
     "ccd_vf", "ccd_ee", "ccd_params_default", "ccd_context_create", "ccd_context_destroy",
     "ccd_context_set_engine", "ccd_context_get_tuning", "ccd_context_set_tuning", "ccd_batch",
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
+    "ccd_context_enable_graphs", "ccd_context_graph_counts",
 ]
 
 
@@ -107,6 +108,8 @@ def _lib():
         L.ccd_context_set_tuning.argtypes = [V, P(Tuning)]
         L.ccd_batch.argtypes = [V, P(BatchDesc), P(ResultSoA), V]
         L.ccd_context_enable_timing.argtypes = [V, ctypes.c_int]
+        L.ccd_context_enable_graphs.argtypes = [V, ctypes.c_int]
+        L.ccd_context_graph_counts.argtypes = [V, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.ccd_context_last_stats.argtypes = [V, P(Stats)]
         L.ccd_strerror.argtypes = [ctypes.c_int]
         L.ccd_strerror.restype = ctypes.c_char_p
@@ -206,6 +209,14 @@ class Context:
         rc = _lib().ccd_context_set_tuning(self._h, ctypes.byref(t))
         if rc != OK:
             raise CCDError(rc, "ccd_context_set_tuning")
+
+    def enable_graphs(self, on: bool = True):
+        _lib().ccd_context_enable_graphs(self._h, 1 if on else 0)
+
+    def graph_counts(self):
+        b, r = ctypes.c_uint64(), ctypes.c_uint64()
+        _lib().ccd_context_graph_counts(self._h, ctypes.byref(b), ctypes.byref(r))
+        return int(b.value), int(r.value)
 
     def enable_timing(self, on: bool = True):
         _lib().ccd_context_enable_timing(self._h, 1 if on else 0)

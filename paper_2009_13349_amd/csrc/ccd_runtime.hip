@@ -81,6 +81,14 @@ struct ccd_context {
     bool timing = false;
     hipEvent_t ev[5] = {};
     bool have_events = false;
+    // hipGraph of the launch sequence, replayed while its parameters are unchanged
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    unsigned char graph_key[512] = {};
+    size_t graph_key_len = 0;
+    uint64_t graph_builds = 0, graph_replays = 0;
     bool last_timed = false;
     bool last_valid = false;
 };
@@ -200,11 +208,12 @@ int ensure_scratch(ccd_context* ctx, const Plan& P) {
     return ok ? CCD_OK : CCD_ENOMEM;
 }
 
-int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool persistent) {
+// Issues the batch's kernel sequence on stream s.
+void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool persistent,
+             bool timed) {
     const int K = ctx->tune.lane_capacity;
     a.counters = (unsigned long long*)ctx->counters.p;
     a.order = nullptr;
-    const bool timed = ctx->timing && ctx->have_events;
     if (timed) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
     if (persistent && a.kind) {
@@ -282,8 +291,72 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
     b.tier = 2;
     hipLaunchKernelGGL((k_group<8, 1>), dim3(P.block_count), dim3(512), 0, s, a, b);
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
+}
+
+// Everything the launch sequence depends on; a graph is reused while this is
+// byte-for-byte unchanged.
+struct LaunchKey {
+    BatchArgs a;
+    Plan P;
+    ccd_tuning tune;
+    void* bufs[7];
+    int32_t persistent, timed;
+};
+
+void drop_graph(ccd_context* ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key_len = 0;
+}
+
+int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool persistent) {
+    const bool timed = ctx->timing && ctx->have_events;
     ctx->last_timed = timed;
     ctx->last_valid = true;
+    // per-kernel timing needs events between the kernels: launch eagerly then
+    if (ctx->use_graphs && ctx->cap_stream && !timed) {
+        LaunchKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.a = a;
+        key.P = P;
+        key.tune = ctx->tune;
+        void* bufs[7] = {ctx->counters.p, ctx->order.p, ctx->lane_arena.p, ctx->rec_a.p,
+                         ctx->group_arena.p, ctx->rec_b.p, ctx->block_arena.p};
+        std::memcpy(key.bufs, bufs, sizeof(bufs));
+        key.persistent = persistent;
+        key.timed = timed;
+        static_assert(sizeof(LaunchKey) <= sizeof(ctx->graph_key), "graph key size");
+        const bool same = ctx->graph_exec && ctx->graph_key_len == sizeof(key) &&
+                          std::memcmp(ctx->graph_key, &key, sizeof(key)) == 0;
+        if (!same) {
+            drop_graph(ctx);
+            bool ok = hip_ok(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
+                             "hipStreamBeginCapture");
+            if (ok) {
+                enqueue(ctx, P, a, ctx->cap_stream, persistent, timed);
+                hipGraph_t g = nullptr;
+                ok = hip_ok(hipStreamEndCapture(ctx->cap_stream, &g), "hipStreamEndCapture");
+                if (ok) {
+                    ctx->graph = g;
+                    ok = hip_ok(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0),
+                                "hipGraphInstantiate");
+                }
+            }
+            if (!ok) {
+                drop_graph(ctx);
+                return CCD_EDEVICE;
+            }
+            std::memcpy(ctx->graph_key, &key, sizeof(key));
+            ctx->graph_key_len = sizeof(key);
+            ctx->graph_builds += 1;
+        } else {
+            ctx->graph_replays += 1;
+        }
+        return hip_ok(hipGraphLaunch(ctx->graph_exec, s), "hipGraphLaunch") ? CCD_OK : CCD_EDEVICE;
+    }
+    enqueue(ctx, P, a, s, persistent, timed);
     return hip_ok(hipGetLastError(), "kernel launch") ? CCD_OK : CCD_EDEVICE;
 }
 
@@ -374,6 +447,8 @@ int ccd_context_create(int device, size_t mem_budget_bytes, ccd_context** out) {
     c->have_events = true;
     for (int i = 0; i < 5; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) c->have_events = false;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        c->cap_stream = nullptr;
     (void)hipGetLastError();
     *out = c;
     return CCD_OK;
@@ -388,6 +463,8 @@ void ccd_context_destroy(ccd_context* c) {
         release(*b);
     if (c->have_events)
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -419,6 +496,20 @@ int ccd_context_set_tuning(ccd_context* c, const ccd_tuning* t) {
     return CCD_OK;
 }
 
+int ccd_context_enable_graphs(ccd_context* c, int enable) {
+    if (!c) return CCD_EINVAL;
+    c->use_graphs = enable != 0;
+    if (!c->use_graphs) drop_graph(c);
+    return CCD_OK;
+}
+
+int ccd_context_graph_counts(ccd_context* c, uint64_t* builds, uint64_t* replays) {
+    if (!c || !builds || !replays) return CCD_EINVAL;
+    *builds = c->graph_builds;
+    *replays = c->graph_replays;
+    return CCD_OK;
+}
+
 int ccd_context_enable_timing(ccd_context* c, int enable) {
     if (!c) return CCD_EINVAL;
     c->timing = enable != 0;
@@ -440,7 +531,10 @@ int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
     out->promoted[1] = h[kCntRecB];
     for (int t = 0; t < 3; ++t) out->lane_slots[t] = h[kCntSlots + t];
     if (c->last_timed)
-        for (int i = 0; i < 4; ++i) (void)hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]);
+        for (int i = 0; i < 4; ++i)
+            if (!hip_ok(hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]),
+                        "hipEventElapsedTime"))
+                out->kernel_ms[i] = 0.0f;
     if (h[kCntError]) return CCD_ENOMEM;
     return CCD_OK;
 }

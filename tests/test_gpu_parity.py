@@ -282,3 +282,30 @@ def test_deep_levels(ctx, torch_dev, scale, delta):
         assert_same(got, ref, what=f"deep levels scale={scale} delta={delta} tuning={tune}")
     r = oracle.solve(0, w["pos"][:, 1], delta)
     assert sum(r.depth) > 64
+
+
+def test_graph_replays_match_eager(ctx, torch_dev):
+    """The captured launch sequence is replayed several times, with eager
+    launches and synchronisations in between; every replay must equal the
+    eager result (and the oracle)."""
+    torch, dev = torch_dev
+    w = W.concat([W.simulation_mixed(6000, seed=40), W.edge_edge_mixed(2000, seed=41)])
+    ref = run_oracle(w, max_iter=200_000)
+    ctx.enable_graphs(False)
+    eager = run_gpu(ctx, torch_dev, w, 0, max_iter=200_000)
+    assert_same(eager, ref, what="eager")
+    ctx.enable_graphs(True)
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    kind = torch.from_numpy(w["kind"]).to(dev)
+    out = None
+    for rep in range(4):
+        out = ctx.batch_device(pos, kind, max_iter=200_000, out=out)
+        torch.cuda.synchronize()
+        got = {k: getattr(out, k).cpu().numpy() for k in FIELDS}
+        got["n_checks"] = got["n_checks"].astype(np.uint64)
+        assert_same(got, ref, what=f"graph replay {rep}")
+        # eager work on the same stream between replays
+        (pos * 2.0).sum().item()
+        torch.cuda.synchronize()
+    builds, replays = ctx.graph_counts()
+    assert builds >= 1 and replays >= 3
