@@ -143,6 +143,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tuning", default="", help="k=v,... overrides of ccd_tuning")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (default: tune once per device and workload, cached)")
+    ap.add_argument("--tuning-cache", default=os.environ.get(
+        "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -172,8 +176,22 @@ def main():
         del src, dst
 
     ctx = ccd.Context(0, mem_budget_bytes=32 << 30)
+    autotune = None
     if args.tuning:
         ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+    elif not args.no_autotune:
+        key = f"{w['name']}_delta{w['delta']:g}"
+        if ctx.tuning_cache_load(args.tuning_cache, key):
+            autotune = {"source": "cache", "tuning": ctx.tuning()}
+        else:
+            ctx.set_engine(ccd.ENGINE_PERSISTENT)
+            t0 = time.perf_counter()
+            best, best_ms = ctx.autotune(pos, kind, delta=w["delta"], max_iter=w["max_iter"],
+                                         min_sep=w["min_sep"])
+            autotune = {"source": "search", "seconds": round(time.perf_counter() - t0, 2),
+                        "best_ms": round(best_ms, 3), "tuning": best}
+            os.makedirs(os.path.dirname(args.tuning_cache) or ".", exist_ok=True)
+            ctx.tuning_cache_store(args.tuning_cache, key)
     t_p, stats_p, out = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps,
                                    args.warmup)
     hits = int(out.hit.sum().item())
@@ -225,6 +243,7 @@ def main():
         "graph_replay": {"value": round(n * args.steps / t_g, 1),
                          "ms_per_step": round(1e3 * t_g / args.steps, 3),
                          "graphs_built": graph_counts[0], "replays": graph_counts[1]},
+        "autotune": autotune,
         "hits": hits,
         "box_checks_per_step": checks_total,
         "sequential_checks_per_step": int(sum(alg_checks)),

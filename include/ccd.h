@@ -144,6 +144,7 @@ typedef struct ccd_tuning {
 int ccd_context_get_tuning(ccd_context* ctx, ccd_tuning* out);
 int ccd_context_set_tuning(ccd_context* ctx, const ccd_tuning* t);
 
+
 /* A batch of n queries in structure-of-arrays layout. */
 typedef struct ccd_batch_desc {
     int64_t n;                 /* number of queries, >= 0 */
@@ -184,6 +185,29 @@ typedef struct ccd_result_soa {
  */
 int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa* out,
               void* stream);
+
+/*
+ * Autotuner: coordinate descent over the ccd_tuning knobs (group occupancy and
+ * count, lane budget, lane capacity, lane waves per CU, group width), each
+ * candidate timed (median of 3, after a warm-up) with events around whole
+ * ccd_batch calls of the given device batch on `stream`; a candidate must be
+ * 2% faster to be taken, and the winner is confirmed against the starting
+ * tuning with 5 runs each.  Leaves the fastest tuning on the context and
+ * returns it with its time.  `out` is overwritten by
+ * every trial.  max_trials <= 0: no limit (about 20 trials).  Results of the
+ * root finder do not depend on the tuning.  Synchronises the stream.
+ */
+int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa* out,
+                 void* stream, int max_trials, ccd_tuning* best, float* best_ms);
+
+/*
+ * Tuning cache in a text file, one line per (GPU architecture, CU count, HIP
+ * runtime version, workload key).  store writes the context's current tuning
+ * under `key` (no whitespace); load applies a matching line, or returns
+ * CCD_EAGAIN when there is none.
+ */
+int ccd_tuning_cache_store(ccd_context* ctx, const char* path, const char* key);
+int ccd_tuning_cache_load(ccd_context* ctx, const char* path, const char* key);
 
 /*
  * The launch sequence of a batch is captured into a hipGraph and replayed while

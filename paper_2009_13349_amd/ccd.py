@@ -26,7 +26,8 @@ EXPORTED = [
     "ccd_vf", "ccd_ee", "ccd_params_default", "ccd_context_create", "ccd_context_destroy",
     "ccd_context_set_engine", "ccd_context_get_tuning", "ccd_context_set_tuning", "ccd_batch",
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
-    "ccd_context_enable_graphs", "ccd_context_graph_counts",
+    "ccd_context_enable_graphs", "ccd_context_graph_counts", "ccd_autotune",
+    "ccd_tuning_cache_store", "ccd_tuning_cache_load",
 ]
 
 
@@ -109,6 +110,10 @@ def _lib():
         L.ccd_batch.argtypes = [V, P(BatchDesc), P(ResultSoA), V]
         L.ccd_context_enable_timing.argtypes = [V, ctypes.c_int]
         L.ccd_context_enable_graphs.argtypes = [V, ctypes.c_int]
+        L.ccd_autotune.argtypes = [V, P(BatchDesc), P(ResultSoA), V, ctypes.c_int, P(Tuning),
+                                   P(ctypes.c_float)]
+        L.ccd_tuning_cache_store.argtypes = [V, ctypes.c_char_p, ctypes.c_char_p]
+        L.ccd_tuning_cache_load.argtypes = [V, ctypes.c_char_p, ctypes.c_char_p]
         L.ccd_context_graph_counts.argtypes = [V, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.ccd_context_last_stats.argtypes = [V, P(Stats)]
         L.ccd_strerror.argtypes = [ctypes.c_int]
@@ -233,11 +238,34 @@ class Context:
         return out
 
     # -- batches -------------------------------------------------------------
-    def batch_device(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
+    def autotune(self, pos, kind=None, max_trials=0, stream=None, **kw) -> tuple[dict, float]:
+        """Runs ccd_autotune on a device batch (same arguments as batch_device);
+        returns (best tuning, its time in ms) and leaves it on the context."""
+        import torch
+        d, o, out, keep, stream = self._device_desc(pos, kind, stream=stream, **kw)
+        t = Tuning()
+        ms = ctypes.c_float()
+        rc = _lib().ccd_autotune(self._h, ctypes.byref(d), ctypes.byref(o),
+                                 ctypes.c_void_p(stream.cuda_stream), int(max_trials),
+                                 ctypes.byref(t), ctypes.byref(ms))
+        if rc != OK:
+            raise CCDError(rc, "ccd_autotune")
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}, float(ms.value)
+
+    def tuning_cache_store(self, path: str, key: str):
+        rc = _lib().ccd_tuning_cache_store(self._h, path.encode(), key.encode())
+        if rc != OK:
+            raise CCDError(rc, "ccd_tuning_cache_store")
+
+    def tuning_cache_load(self, path: str, key: str) -> bool:
+        rc = _lib().ccd_tuning_cache_load(self._h, path.encode(), key.encode())
+        if rc not in (OK, EAGAIN):
+            raise CCDError(rc, "ccd_tuning_cache_load")
+        return rc == OK
+
+    def _device_desc(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
                      min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
-                     out: BatchResult | None = None, stream=None) -> BatchResult:
-        """Asynchronous batch on device tensors (torch): pos float64 [24, n],
-        kind uint8 [n].  Results are torch tensors on the same device."""
+                     out: BatchResult | None = None, stream=None):
         import torch
         assert pos.is_cuda and pos.dtype == torch.float64 and pos.dim() == 2 and pos.shape[0] == 24
         pos = pos.contiguous()
@@ -273,6 +301,16 @@ class Context:
                       out.n_checks.data_ptr(), out.status.data_ptr())
         if stream is None:
             stream = torch.cuda.current_stream(dev)
+        return d, o, out, keep, stream
+
+    def batch_device(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
+                     min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
+                     out: BatchResult | None = None, stream=None) -> BatchResult:
+        """Asynchronous batch on device tensors (torch): pos float64 [24, n],
+        kind uint8 [n].  Results are torch tensors on the same device."""
+        d, o, out, keep, stream = self._device_desc(
+            pos, kind, default_kind, delta, max_iter, min_sep, literal, delta_q, max_iter_q,
+            min_sep_q, out, stream)
         rc = _lib().ccd_batch(self._h, ctypes.byref(d), ctypes.byref(o),
                               ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/ccd.h"
@@ -658,6 +659,197 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
     rc = ensure_scratch(ctx, P);
     if (rc != CCD_OK) return rc;
     return launch(ctx, P, a, s, persistent);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate descent over the launch/capacity knobs, each candidate
+// timed with events around whole batches.  Results do not depend on tuning, so
+// the search only trades speed.
+
+namespace {
+
+float time_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* out,
+                 hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, int* rc) {
+    *rc = ccd_batch(ctx, d, out, s);  // warm-up (also builds the graph)
+    if (*rc != CCD_OK) return -1.0f;
+    std::vector<float> t;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, s);
+        *rc = ccd_batch(ctx, d, out, s);
+        if (*rc != CCD_OK) return -1.0f;
+        (void)hipEventRecord(e1, s);
+        if (!hip_ok(hipEventSynchronize(e1), "hipEventSynchronize")) {
+            *rc = CCD_EDEVICE;
+            return -1.0f;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* out,
+                 void* stream, int max_trials, ccd_tuning* best_out, float* best_ms_out) {
+    if (!ctx || !d || !out || !d->on_device) return CCD_EINVAL;
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (!hip_ok(hipEventCreate(&e0), "hipEventCreate")) return CCD_EDEVICE;
+    if (!hip_ok(hipEventCreate(&e1), "hipEventCreate")) {
+        (void)hipEventDestroy(e0);
+        return CCD_EDEVICE;
+    }
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    const int cu = ctx->num_cu;
+    const ccd_tuning start = ctx->tune;
+    ccd_tuning best = ctx->tune;
+    int rc = CCD_OK;
+    int trials = 0;
+    float best_ms = time_batch(ctx, d, out, s, e0, e1, 3, &rc);
+    ++trials;
+    // knob candidates; group_count follows the occupancy (4 SIMDs per CU)
+    struct Knob { int id; std::vector<int64_t> vals; };
+    const std::vector<Knob> knobs = {
+        {0, {2, 3, 4}},            // group_occupancy (with group_count = 4 * cu * occ)
+        {1, {32, 64, 128, 256, 512}},  // lane_budget
+        {2, {16, 32, 64}},         // lane_capacity
+        {3, {4, 8, 12}},           // lane_waves_per_cu
+        {4, {1, 2}},               // group_waves
+    };
+    for (int pass = 0; pass < 2 && rc == CCD_OK; ++pass) {
+        bool improved = false;
+        for (const Knob& k : knobs) {
+            for (int64_t v : k.vals) {
+                if (max_trials > 0 && trials >= max_trials) break;
+                ccd_tuning t = best;
+                switch (k.id) {
+                    case 0: t.group_occupancy = (int32_t)v; t.group_count = (int32_t)(4 * cu * v); break;
+                    case 1: t.lane_budget = v; break;
+                    case 2: t.lane_capacity = (int32_t)v; break;
+                    case 3: t.lane_waves_per_cu = (int32_t)v; break;
+                    case 4: t.group_waves = (int32_t)v;
+                            t.group_count = (int32_t)(v == 1 ? 4 * cu * t.group_occupancy : 4 * cu * 2 / v);
+                            break;
+                }
+                clamp_tuning(t);
+                if (std::memcmp(&t, &best, sizeof(t)) == 0) continue;
+                ctx->tune = t;
+                const float ms = time_batch(ctx, d, out, s, e0, e1, 3, &rc);
+                ++trials;
+                if (rc != CCD_OK) break;
+                if (ms > 0.0f && ms < best_ms * 0.98f) {
+                    best_ms = ms;
+                    best = t;
+                    improved = true;
+                }
+            }
+            if (rc != CCD_OK) break;
+        }
+        if (!improved) break;
+    }
+    // confirm against the starting point with more repetitions
+    if (rc == CCD_OK && std::memcmp(&best, &start, sizeof(best)) != 0) {
+        ctx->tune = start;
+        const float ms_start = time_batch(ctx, d, out, s, e0, e1, 5, &rc);
+        ctx->tune = best;
+        const float ms_best = rc == CCD_OK ? time_batch(ctx, d, out, s, e0, e1, 5, &rc) : -1.0f;
+        if (rc == CCD_OK && !(ms_best < ms_start)) {
+            best = start;
+            best_ms = ms_start;
+        } else if (rc == CCD_OK) {
+            best_ms = ms_best;
+        }
+    }
+    ctx->tune = best;
+    ctx->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != CCD_OK) return rc;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
+    return CCD_OK;
+}
+
+// Tuning cache: one line per (device, workload key):
+//   <arch> <cus> <hip-version> <key> <the eight ccd_tuning fields>
+namespace {
+void device_tag(ccd_context* ctx, char* arch, size_t n, int* hipver) {
+    hipDeviceProp_t prop;
+    std::snprintf(arch, n, "unknown");
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess)
+        std::snprintf(arch, n, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    *hipver = 0;
+    (void)hipRuntimeGetVersion(hipver);
+    (void)hipGetLastError();
+}
+}  // namespace
+
+int ccd_tuning_cache_store(ccd_context* ctx, const char* path, const char* key) {
+    if (!ctx || !path || !key || !*key || std::strpbrk(key, " \t\n")) return CCD_EINVAL;
+    char arch[128];
+    int ver;
+    device_tag(ctx, arch, sizeof(arch), &ver);
+    std::vector<std::string> keep;
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof(line), f)) {
+            char a[128], k[128];
+            int c, v;
+            if (std::sscanf(line, "%127s %d %d %127s", a, &c, &v, k) == 4 &&
+                std::strcmp(a, arch) == 0 && c == ctx->num_cu && v == ver && std::strcmp(k, key) == 0)
+                continue;
+            keep.emplace_back(line);
+        }
+        std::fclose(f);
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) return CCD_EINVAL;
+    for (const std::string& l : keep) std::fputs(l.c_str(), f);
+    const ccd_tuning& t = ctx->tune;
+    std::fprintf(f, "%s %d %d %s %d %d %lld %d %d %lld %d %d\n", arch, ctx->num_cu, ver, key,
+                 t.lane_waves_per_cu, t.lane_capacity, (long long)t.lane_budget, t.group_waves,
+                 t.group_count, (long long)t.group_capacity, t.block_count, t.group_occupancy);
+    std::fclose(f);
+    return CCD_OK;
+}
+
+int ccd_tuning_cache_load(ccd_context* ctx, const char* path, const char* key) {
+    if (!ctx || !path || !key) return CCD_EINVAL;
+    char arch[128];
+    int ver;
+    device_tag(ctx, arch, sizeof(arch), &ver);
+    FILE* f = std::fopen(path, "r");
+    if (!f) return CCD_EAGAIN;
+    char line[512];
+    int found = 0;
+    ccd_tuning t = ctx->tune;
+    while (std::fgets(line, sizeof(line), f)) {
+        char a[128], k[128];
+        int c, v;
+        long long lb, gc;
+        ccd_tuning r{};
+        if (std::sscanf(line, "%127s %d %d %127s %d %d %lld %d %d %lld %d %d", a, &c, &v, k,
+                        &r.lane_waves_per_cu, &r.lane_capacity, &lb, &r.group_waves, &r.group_count,
+                        &gc, &r.block_count, &r.group_occupancy) == 12 &&
+            std::strcmp(a, arch) == 0 && c == ctx->num_cu && v == ver && std::strcmp(k, key) == 0) {
+            r.lane_budget = lb;
+            r.group_capacity = gc;
+            t = r;
+            found = 1;
+        }
+    }
+    std::fclose(f);
+    if (!found) return CCD_EAGAIN;
+    clamp_tuning(t);
+    ctx->tune = t;
+    return CCD_OK;
 }
 
 int ccd_vf(const double x0[4][3], const double x1[4][3], const ccd_params* p, ccd_result* out) {

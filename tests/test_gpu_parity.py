@@ -309,3 +309,21 @@ def test_graph_replays_match_eager(ctx, torch_dev):
         torch.cuda.synchronize()
     builds, replays = ctx.graph_counts()
     assert builds >= 1 and replays >= 3
+
+
+def test_autotune_and_cache(ctx, torch_dev, tmp_path):
+    torch, dev = torch_dev
+    w = W.concat([W.simulation_mixed(20000, seed=50), W.edge_edge_mixed(2000, seed=51)])
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    kind = torch.from_numpy(w["kind"]).to(dev)
+    best, ms = ctx.autotune(pos, kind, max_trials=8)
+    assert ms > 0 and best == ctx.tuning()
+    ref = run_oracle(w)
+    assert_same(run_gpu(ctx, torch_dev, w, 0), ref, what="after autotune")
+    path = str(tmp_path / "tuning.txt")
+    ctx.tuning_cache_store(path, "sim22k")
+    from paper_2009_13349_amd import ccd
+    with ccd.Context(0) as c2:
+        assert not c2.tuning_cache_load(path, "other")
+        assert c2.tuning_cache_load(path, "sim22k")
+        assert c2.tuning() == best
