@@ -231,6 +231,74 @@ typedef struct ccd_stats {
 int ccd_context_enable_timing(ccd_context* ctx, int enable);
 int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
 
+/* ------------------------------------------------------------------------- */
+/*
+ * Serving: continuous batching of requests on one GPU.
+ *
+ * A request is a batch of queries in host memory (ccd_batch_desc with
+ * on_device = 0 and no per-query parameter arrays; its params apply to all of
+ * its queries).  A scheduler thread admits requests in arrival order while the
+ * device pool has room for their inputs and outputs, and whenever a compute
+ * stream is idle it launches one pass of the root finder over every admitted
+ * request not yet started (their queries concatenated).  Requests arriving
+ * meanwhile go into the next launch on another stream, overlapping the first.
+ * Each request's results are bit-identical to ccd_batch on it alone.
+ *
+ * The caller's input and output arrays must stay valid until the ticket is
+ * done.  Inputs in pinned host memory (hipHostMalloc) are copied
+ * asynchronously; pageable inputs make the scheduler wait for their copy.
+ * Results are staged in pinned memory owned by the server and copied into the
+ * caller's arrays before the ticket completes.
+ */
+typedef struct ccd_server ccd_server;
+
+typedef struct ccd_serve_config {
+    int32_t device;
+    int32_t streams;                /* compute streams (1..4), default 2 */
+    int32_t max_requests;           /* requests per launch, default 1024 */
+    int32_t reserved;
+    int64_t max_queries_per_launch; /* default 4,000,000 (a larger single request still runs) */
+    size_t pool_bytes;              /* device memory for resident requests, default 8 GiB */
+    size_t scratch_bytes;           /* scratch budget per compute stream, default 12 GiB */
+} ccd_serve_config;
+
+typedef struct ccd_serve_info {
+    int32_t state;     /* 0 queued, 1 admitted, 2 running, 3 done */
+    int32_t rc;        /* CCD_OK or the request's error once done */
+    int64_t n;
+    double t_submit;   /* host steady-clock seconds */
+    double t_admit;
+    double t_launch;
+    double t_done;     /* results are in the caller's arrays */
+} ccd_serve_info;
+
+typedef struct ccd_serve_stats {
+    uint64_t submitted, admitted, completed, rejected, launches, queries_completed;
+    uint64_t queued;       /* waiting for device memory */
+    uint64_t pool_bytes, pool_in_use, pool_peak;
+} ccd_serve_stats;
+
+#define CCD_SERVE_NONBLOCKING 0x1 /* submit returns CCD_EAGAIN instead of queueing when the
+                                     request cannot be admitted right away */
+
+void ccd_serve_config_default(ccd_serve_config* cfg);
+/* cfg NULL: defaults.  CCD_ENOMEM if the pools or scratch cannot be allocated. */
+int ccd_serve_open(const ccd_serve_config* cfg, ccd_server** out);
+/* Validates the request on the host (CCD_EINVAL), rejects one larger than the
+ * pool (CCD_ENOMEM), then queues it and returns its ticket. */
+int ccd_serve_submit(ccd_server* s, const ccd_batch_desc* desc, const ccd_result_soa* out,
+                     int flags, int64_t* ticket);
+/* 1 done (results in place), 0 pending, or the request's negative error code. */
+int ccd_serve_poll(ccd_server* s, int64_t ticket);
+/* Blocks until done (timeout_ms < 0: no limit); CCD_ETIMEDOUT otherwise. */
+int ccd_serve_wait(ccd_server* s, int64_t ticket, int timeout_ms);
+int ccd_serve_query(ccd_server* s, int64_t ticket, ccd_serve_info* info);
+/* Forgets a finished ticket (CCD_EAGAIN while it is not done). */
+int ccd_serve_release(ccd_server* s, int64_t ticket);
+int ccd_serve_stats_get(ccd_server* s, ccd_serve_stats* out);
+/* Finishes every submitted request, then frees the server. */
+int ccd_serve_close(ccd_server* s);
+
 /* Message for a return code. */
 const char* ccd_strerror(int code);
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccd.so")
-SOURCES = ["ccd_kernels.hip", "ccd_runtime.hip"]
+SOURCES = ["ccd_kernels.hip", "ccd_runtime.hip", "ccd_serve.hip"]
 ARCH = os.environ.get("CCD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -36,7 +36,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -350,3 +350,158 @@ class Context:
         if rc != OK:
             raise CCDError(rc, "ccd_batch")
         return res
+
+
+# ---------------------------------------------------------------------------
+# Serving
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("max_requests", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_queries_per_launch", ctypes.c_int64), ("pool_bytes", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t)]
+
+
+class ServeInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("rc", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("submitted", "admitted", "completed", "rejected", "launches", "queries_completed",
+                 "queued", "pool_bytes", "pool_in_use", "pool_peak")]
+
+
+SERVE_NONBLOCKING = 0x1
+EXPORTED += ["ccd_serve_config_default", "ccd_serve_open", "ccd_serve_submit", "ccd_serve_poll",
+             "ccd_serve_wait", "ccd_serve_query", "ccd_serve_release", "ccd_serve_stats_get",
+             "ccd_serve_close"]
+
+
+def _serve_lib():
+    L = _lib()
+    if not getattr(L, "_serve_ready", False):
+        V, P = ctypes.c_void_p, ctypes.POINTER
+        L.ccd_serve_config_default.argtypes = [P(ServeConfig)]
+        L.ccd_serve_config_default.restype = None
+        L.ccd_serve_open.argtypes = [P(ServeConfig), P(V)]
+        L.ccd_serve_submit.argtypes = [V, P(BatchDesc), P(ResultSoA), ctypes.c_int, P(ctypes.c_int64)]
+        L.ccd_serve_poll.argtypes = [V, ctypes.c_int64]
+        L.ccd_serve_wait.argtypes = [V, ctypes.c_int64, ctypes.c_int]
+        L.ccd_serve_query.argtypes = [V, ctypes.c_int64, P(ServeInfo)]
+        L.ccd_serve_release.argtypes = [V, ctypes.c_int64]
+        L.ccd_serve_stats_get.argtypes = [V, P(ServeStats)]
+        L.ccd_serve_close.argtypes = [V]
+        L._serve_ready = True
+    return L
+
+
+class Ticket:
+    """A submitted request: its id, and the arrays it reads and writes."""
+
+    def __init__(self, tid, keep, result: BatchResult):
+        self.id = tid
+        self._keep = keep
+        self.result = result
+
+
+class Server:
+    """Continuous-batching server (ccd_serve_*) on one GPU."""
+
+    def __init__(self, device=0, streams=2, pool_bytes=8 << 30, scratch_bytes=12 << 30,
+                 max_queries_per_launch=4_000_000, max_requests=1024):
+        L = _serve_lib()
+        c = ServeConfig()
+        L.ccd_serve_config_default(ctypes.byref(c))
+        c.device, c.streams, c.max_requests = device, streams, max_requests
+        c.max_queries_per_launch, c.pool_bytes, c.scratch_bytes = (
+            max_queries_per_launch, pool_bytes, scratch_bytes)
+        h = ctypes.c_void_p()
+        rc = L.ccd_serve_open(ctypes.byref(c), ctypes.byref(h))
+        if rc != OK:
+            raise CCDError(rc, "ccd_serve_open")
+        self._h = h
+        # The server reads the inputs and writes the outputs of a request until
+        # it is done: keep every submitted ticket (and its arrays) alive until
+        # release() or close(), whatever the caller does with its references.
+        self._live = {}
+
+    def submit(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000, min_sep=0.0,
+               literal=False, nonblocking=False, out: BatchResult | None = None) -> Ticket:
+        """pos: host array float64 [24, n] (numpy, or a pinned torch CPU tensor)."""
+        def host(a, dt):
+            if hasattr(a, "data_ptr"):
+                return a, a.data_ptr()
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            return a, a.ctypes.data
+        pos, pos_ptr = host(pos, np.float64)
+        n = pos.shape[1]
+        keep = [pos]
+        d = BatchDesc()
+        d.n, d.pos, d.default_kind = n, pos_ptr, default_kind
+        if kind is not None:
+            kind, kptr = host(kind, np.uint8)
+            keep.append(kind)
+            d.kind = kptr
+        d.params = params(delta, max_iter, min_sep, literal)
+        d.on_device = 0
+        if out is None:
+            out = BatchResult(toi=np.empty(n), t_width=np.empty(n), hit=np.empty(n, np.uint8),
+                              n_checks=np.empty(n, np.uint64), status=np.empty(n, np.uint8))
+        o = ResultSoA(*(getattr(out, k).ctypes.data for k in ("toi", "t_width", "hit", "n_checks",
+                                                             "status")))
+        t = ctypes.c_int64()
+        rc = _serve_lib().ccd_serve_submit(self._h, ctypes.byref(d), ctypes.byref(o),
+                                           SERVE_NONBLOCKING if nonblocking else 0, ctypes.byref(t))
+        if rc != OK:
+            raise CCDError(rc, "ccd_serve_submit")
+        tk = Ticket(int(t.value), keep, out)
+        self._live[tk.id] = tk
+        return tk
+
+    def poll(self, t: Ticket) -> int:
+        return _serve_lib().ccd_serve_poll(self._h, t.id)
+
+    def wait(self, t: Ticket, timeout_ms: int = -1) -> BatchResult:
+        rc = _serve_lib().ccd_serve_wait(self._h, t.id, int(timeout_ms))
+        if rc != OK:
+            raise CCDError(rc, "ccd_serve_wait")
+        return t.result
+
+    def info(self, t: Ticket) -> dict:
+        i = ServeInfo()
+        rc = _serve_lib().ccd_serve_query(self._h, t.id, ctypes.byref(i))
+        if rc != OK:
+            raise CCDError(rc, "ccd_serve_query")
+        return {f: getattr(i, f) for f, _ in ServeInfo._fields_}
+
+    def release(self, t: Ticket):
+        rc = _serve_lib().ccd_serve_release(self._h, t.id)
+        if rc == OK:
+            self._live.pop(t.id, None)
+        return rc
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        _serve_lib().ccd_serve_stats_get(self._h, ctypes.byref(s))
+        return {f: int(getattr(s, f)) for f, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _serve_lib().ccd_serve_close(self._h)  # finishes every submitted request
+            self._h = None
+            self._live = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

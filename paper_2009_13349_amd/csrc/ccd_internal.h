@@ -19,7 +19,28 @@ enum Counter : int {
     kCntEnd = kCntSlots + 3,
 };
 
+// One request of a serving launch: its queries occupy the global indices
+// [base, base + n) of the launch.
+struct ReqEntry {
+    int64_t base;
+    int64_t n;
+    const double* pos;      // [24][n]
+    const uint8_t* kind;    // [n] or null
+    double delta;
+    int64_t max_iter;
+    double min_sep;
+    uint32_t flags;
+    uint32_t default_kind;
+    double* toi;
+    double* t_width;
+    uint8_t* hit;
+    uint64_t* n_checks;
+    uint8_t* status;
+};
+
 // Inputs, parameters and outputs of one batch (passed by value to kernels).
+// With reqs != null the launch covers nreq requests (sorted by base) and the
+// per-batch fields below other than n are unused; n is the total query count.
 struct BatchArgs {
     int64_t n;
     const double* pos;          // [24][n]
@@ -39,6 +60,8 @@ struct BatchArgs {
     uint8_t* status;
     unsigned long long* counters;  // [kCntEnd]
     const int64_t* order;          // [n] query order grouped by kind, or null (identity)
+    const ReqEntry* reqs;          // serving: request table, or null
+    int64_t nreq;
 };
 
 // A query handed from one engine to the next, at the start of a level.  The

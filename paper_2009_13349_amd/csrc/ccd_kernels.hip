@@ -71,14 +71,69 @@ struct Outcome {
     uint8_t st;
 };
 
-__device__ __forceinline__ void load_query(const BatchArgs& a, int64_t q, Query& Q, bool& valid) {
+// Where the global query index v of a launch lives: a plain batch, or one of
+// the requests of a serving launch (binary search of the request table).
+struct QView {
+    const double* pos;
+    int64_t n;  // queries of its batch / request
+    int64_t q;  // index within it
+    const uint8_t* kind;
+    uint32_t default_kind;
+    const double* delta_q;
+    const int64_t* max_iter_q;
+    const double* min_sep_q;
+    double delta;
+    int64_t max_iter;
+    double min_sep;
+    uint32_t flags;
+    double* toi;
+    double* t_width;
+    uint8_t* hit;
+    uint64_t* n_checks;
+    uint8_t* status;
+};
+
+__device__ __forceinline__ QView view(const BatchArgs& a, int64_t v) {
+    QView w;
+    if (!a.reqs) {
+        w.pos = a.pos; w.n = a.n; w.q = v; w.kind = a.kind; w.default_kind = a.default_kind;
+        w.delta_q = a.delta_q; w.max_iter_q = a.max_iter_q; w.min_sep_q = a.min_sep_q;
+        w.delta = a.delta; w.max_iter = a.max_iter; w.min_sep = a.min_sep; w.flags = a.flags;
+        w.toi = a.toi; w.t_width = a.t_width; w.hit = a.hit; w.n_checks = a.n_checks;
+        w.status = a.status;
+        return w;
+    }
+    int64_t lo = 0, hi = a.nreq - 1;  // last entry with base <= v
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (a.reqs[mid].base <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    const ReqEntry& r = a.reqs[lo];
+    w.pos = r.pos; w.n = r.n; w.q = v - r.base; w.kind = r.kind; w.default_kind = r.default_kind;
+    w.delta_q = nullptr; w.max_iter_q = nullptr; w.min_sep_q = nullptr;
+    w.delta = r.delta; w.max_iter = r.max_iter; w.min_sep = r.min_sep; w.flags = r.flags;
+    w.toi = r.toi; w.t_width = r.t_width; w.hit = r.hit; w.n_checks = r.n_checks;
+    w.status = r.status;
+    return w;
+}
+
+__device__ __forceinline__ int query_kind(const BatchArgs& a, int64_t v) {
+    if (!a.reqs) return a.kind ? (int)a.kind[v] : (int)a.default_kind;
+    const QView w = view(a, v);
+    return w.kind ? (int)w.kind[w.q] : (int)w.default_kind;
+}
+
+__device__ __forceinline__ void load_query(const BatchArgs& a, int64_t v, Query& Q, bool& valid) {
+    const QView w = view(a, v);
+    const int64_t q = w.q;
 #pragma unroll
-    for (int r = 0; r < 24; ++r) Q.X[r] = a.pos[(int64_t)r * a.n + q];
-    Q.kind = a.kind ? (int)a.kind[q] : (int)a.default_kind;
-    Q.delta = a.delta_q ? a.delta_q[q] : a.delta;
-    Q.max_iter = a.max_iter_q ? a.max_iter_q[q] : a.max_iter;
-    Q.min_sep = a.min_sep_q ? a.min_sep_q[q] : a.min_sep;
-    Q.literal = (a.flags & kFlagLiteral) != 0;
+    for (int r = 0; r < 24; ++r) Q.X[r] = w.pos[(int64_t)r * w.n + q];
+    Q.kind = w.kind ? (int)w.kind[q] : (int)w.default_kind;
+    Q.delta = w.delta_q ? w.delta_q[q] : w.delta;
+    Q.max_iter = w.max_iter_q ? w.max_iter_q[q] : w.max_iter;
+    Q.min_sep = w.min_sep_q ? w.min_sep_q[q] : w.min_sep;
+    Q.literal = (w.flags & kFlagLiteral) != 0;
     double gmin;
     filter_eps(Q.kind, Q.X, Q.min_sep, Q.eps, &gmin);
     valid = (Q.kind == kVF || Q.kind == kEE) && query_valid(Q.X, Q.delta, Q.max_iter, Q.min_sep, gmin);
@@ -209,20 +264,24 @@ __device__ __forceinline__ void advance(State& S, const Acc& A, bool literal, co
     S.cnt = next_cnt;
 }
 
-__device__ __forceinline__ void write_result(const BatchArgs& a, int64_t q, const Outcome& O) {
-    a.toi[q] = O.toi;
-    a.t_width[q] = O.tw;
-    a.hit[q] = (O.toi <= 1.0) ? 1 : 0;
-    a.n_checks[q] = O.n;
-    a.status[q] = O.st;
+__device__ __forceinline__ void write_result(const BatchArgs& a, int64_t v, const Outcome& O) {
+    const QView w = view(a, v);
+    const int64_t q = w.q;
+    w.toi[q] = O.toi;
+    w.t_width[q] = O.tw;
+    w.hit[q] = (O.toi <= 1.0) ? 1 : 0;
+    w.n_checks[q] = O.n;
+    w.status[q] = O.st;
 }
 
-__device__ __forceinline__ void write_invalid(const BatchArgs& a, int64_t q) {
-    a.toi[q] = __longlong_as_double(0x7ff8000000000000ll);
-    a.t_width[q] = __longlong_as_double(0x7ff8000000000000ll);
-    a.hit[q] = 0;
-    a.n_checks[q] = 0;
-    a.status[q] = kStInvalid;
+__device__ __forceinline__ void write_invalid(const BatchArgs& a, int64_t v) {
+    const QView w = view(a, v);
+    const int64_t q = w.q;
+    w.toi[q] = __longlong_as_double(0x7ff8000000000000ll);
+    w.t_width[q] = __longlong_as_double(0x7ff8000000000000ll);
+    w.hit[q] = 0;
+    w.n_checks[q] = 0;
+    w.status[q] = kStInvalid;
 }
 
 template <int KIND>
@@ -355,7 +414,7 @@ __device__ __forceinline__ void acc_uniform(Acc& A) {
 __global__ void k_partition(BatchArgs a, int64_t* order) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool act = q < a.n;
-    const int kind = act ? (a.kind ? (int)a.kind[q] : (int)a.default_kind) : 0;
+    const int kind = act ? query_kind(a, q) : 0;
     const bool ee = act && kind == kEE;
     const bool vf = act && !ee;
     const uint64_t mv = __ballot(vf), me = __ballot(ee);
@@ -878,8 +937,6 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
     const int64_t in_k = (g.in_record_words - kRecordHeaderWords) / 3;
     uint64_t nchk[2] = {0, 0};
     uint64_t slots = 0;
-    const bool literal = (a.flags & kFlagLiteral) != 0;
-
     while (true) {
         if (tid == 0) sh.rec = (int64_t)atomicAdd(&a.counters[g.in_take_idx], 1ull);
         __syncthreads();
@@ -887,14 +944,16 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         if (r >= in_count) break;
         const uint64_t* rec = g.in_records + r * g.in_record_words;
         const Record h = *reinterpret_cast<const Record*>(rec);
-        const int64_t q = h.q;
-        const int kind = a.kind ? (int)a.kind[q] : (int)a.default_kind;
-        const double delta = a.delta_q ? a.delta_q[q] : a.delta;
-        const int64_t max_iter = a.max_iter_q ? a.max_iter_q[q] : a.max_iter;
-        const double min_sep = a.min_sep_q ? a.min_sep_q[q] : a.min_sep;
+        const QView qv = view(a, h.q);
+        const int64_t q = qv.q;
+        const int kind = qv.kind ? (int)qv.kind[q] : (int)qv.default_kind;
+        const double delta = qv.delta_q ? qv.delta_q[q] : qv.delta;
+        const int64_t max_iter = qv.max_iter_q ? qv.max_iter_q[q] : qv.max_iter;
+        const double min_sep = qv.min_sep_q ? qv.min_sep_q[q] : qv.min_sep;
+        const bool literal = (qv.flags & kFlagLiteral) != 0;
         if (tid < 24) {
             const int c = tid % 3, k = tid / 3;
-            sh.Xs[c * 8 + k] = a.pos[(int64_t)tid * a.n + q];
+            sh.Xs[c * 8 + k] = qv.pos[(int64_t)tid * qv.n + q];
         }
         const uint64_t* rb = rec + kRecordHeaderWords;
         if (depth_sum(h.d) <= 64) {

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/ccd.h"
+#include "ccd_host.h"
 #include "ccd_internal.h"
 
 namespace ccd {
@@ -83,7 +84,7 @@ struct ccd_context {
     hipEvent_t ev[5] = {};
     bool have_events = false;
     // hipGraph of the launch sequence, replayed while its parameters are unchanged
-    bool use_graphs = true;
+    bool use_graphs = true;  // (serving contexts launch eagerly: their arguments change per launch)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -217,7 +218,7 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
     a.order = nullptr;
     if (timed) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
-    if (persistent && a.kind) {
+    if (persistent && (a.kind || a.reqs)) {
         hipLaunchKernelGGL(k_partition, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, a,
                            (int64_t*)ctx->order.p);
         a.order = (const int64_t*)ctx->order.p;
@@ -360,6 +361,42 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
     enqueue(ctx, P, a, s, persistent, timed);
     return hip_ok(hipGetLastError(), "kernel launch") ? CCD_OK : CCD_EDEVICE;
 }
+
+}  // namespace
+
+namespace ccd {
+
+// Plans scratch for a launch of a.n queries whose largest m_I is mi_max,
+// grows the context's buffers and enqueues the kernel sequence on s.
+int run_args(ccd_context* ctx, BatchArgs a, int64_t mi_max, hipStream_t s) {
+    const bool persistent = ctx->engine == CCD_ENGINE_PERSISTENT;
+    Plan P;
+    int rc = make_plan(ctx, a.n, std::max<int64_t>(mi_max, 1), persistent, P);
+    if (rc != CCD_OK) return rc;
+    rc = ensure_scratch(ctx, P);
+    if (rc != CCD_OK) return rc;
+    return launch(ctx, P, a, s, persistent);
+}
+
+int reserve(ccd_context* ctx, int64_t n, int64_t mi_max) {
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    Plan P;
+    int rc = make_plan(ctx, n, std::max<int64_t>(mi_max, 1), ctx->engine == CCD_ENGINE_PERSISTENT, P);
+    if (rc != CCD_OK) return rc;
+    return ensure_scratch(ctx, P);
+}
+
+bool host_valid(const double X[24], int kind, double delta, int64_t max_iter, double min_sep) {
+    return host_query_valid(X, kind, delta, max_iter, min_sep);
+}
+
+bool record_hip(hipError_t e, const char* what) { return hip_ok(e, what); }
+
+void set_last_error(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
+}  // namespace ccd
+
+namespace {
 
 std::mutex g_default_mu;
 ccd_context* g_default = nullptr;
@@ -609,12 +646,7 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
         a.hit = (uint8_t*)(base + o_hit);
         a.n_checks = (uint64_t*)(base + o_nc);
         a.status = (uint8_t*)(base + o_st);
-        Plan P;
-        int rc = make_plan(ctx, n, mi_max, persistent, P);
-        if (rc != CCD_OK) return rc;
-        rc = ensure_scratch(ctx, P);
-        if (rc != CCD_OK) return rc;
-        rc = launch(ctx, P, a, s, persistent);
+        int rc = ccd::run_args(ctx, a, mi_max, s);
         if (rc != CCD_OK) return rc;
         unsigned long long err = 0;
         ok = hip_ok(hipMemcpyAsync(out->toi, a.toi, n * 8, hipMemcpyDeviceToHost, s), "copy toi") &&
@@ -653,12 +685,7 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
     a.hit = out->hit;
     a.n_checks = out->n_checks;
     a.status = out->status;
-    Plan P;
-    int rc = make_plan(ctx, n, std::max<int64_t>(mi_max, 1), persistent, P);
-    if (rc != CCD_OK) return rc;
-    rc = ensure_scratch(ctx, P);
-    if (rc != CCD_OK) return rc;
-    return launch(ctx, P, a, s, persistent);
+    return ccd::run_args(ctx, a, mi_max, s);
 }
 
 // ---------------------------------------------------------------------------
