@@ -133,6 +133,61 @@ def cpu_baseline(w, seconds: float):
                       f"{n}-query workload, single-threaded C++ oracle, {t_used:.1f} s"}
 
 
+def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 32, load: float = 0.7,
+                  seed: int = 4):
+    """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
+    log-uniform in [1e-6, 1e-4]) at `load` x the measured batch throughput,
+    submitted to the continuous-batching server; latency = scheduled arrival ->
+    results in the caller's arrays.  Request payloads are contiguous pinned
+    slices of the benchmark workload (a fixed set of `payloads` of them,
+    reused round robin)."""
+    import math
+    from paper_2009_13349_amd import ccd
+    rng = np.random.default_rng(seed)
+    N = w["pos"].shape[1]
+    sizes = np.round(np.exp(rng.uniform(math.log(1e3), math.log(1e6), size=payloads))).astype(int)
+    pay = []
+    for n in sizes:
+        off = int(rng.integers(0, N - n + 1))
+        pos = torch.from_numpy(np.ascontiguousarray(w["pos"][:, off:off + n])).pin_memory()
+        kind = torch.from_numpy(np.ascontiguousarray(w["kind"][off:off + n])).pin_memory()
+        pay.append((int(n), pos, kind))
+    mean_n = float(np.mean(sizes))
+    lam = load * q_sat / mean_n  # requests per second
+    gaps = rng.exponential(1.0 / lam, size=requests)
+    deltas = np.exp(rng.uniform(math.log(1e-6), math.log(1e-4), size=requests))
+    srv = ccd.Server(streams=2, pool_bytes=16 << 30, scratch_bytes=12 << 30,
+                     max_queries_per_launch=4_000_000)
+    # warm-up: one request of each payload size, not timed
+    for n, pos, kind in pay[:4]:
+        srv.wait(srv.submit(pos, kind, delta=1e-6), 600_000)
+    t0 = time.monotonic() + 0.05
+    arrivals = t0 + np.cumsum(gaps)
+    tickets = []
+    for i in range(requests):
+        dt = arrivals[i] - time.monotonic()
+        if dt > 0:
+            time.sleep(dt)
+        n, pos, kind = pay[i % payloads]
+        tickets.append((srv.submit(pos, kind, delta=float(deltas[i])), arrivals[i], n))
+    lat, t_end, qsum = [], 0.0, 0
+    for t, arr, n in tickets:
+        srv.wait(t, 600_000)
+        info = srv.info(t)
+        lat.append(info["t_done"] - arr)
+        t_end = max(t_end, info["t_done"])
+        qsum += n
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat[len(lat) // 20:]) * 1e3  # drop the first 5% (warm-up of the stream)
+    return {"requests": requests, "offered_load": load, "offered_requests_per_s": round(lam, 2),
+            "mean_request_queries": round(mean_n, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3),
+            "queries_per_s": round(qsum / (t_end - t0), 1), "launches": st["launches"],
+            "pool_peak_bytes": st["pool_peak"],
+            "latency": "scheduled arrival -> results in the caller's host arrays"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +202,8 @@ def main():
                     help="skip the autotuner (default: tune once per device and workload, cached)")
     ap.add_argument("--tuning-cache", default=os.environ.get(
         "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving measurement (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -253,6 +310,8 @@ def main():
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,
     }
+    line["serve"] = (serve_latency(w, torch, value, args.serve_requests)
+                     if args.serve_requests > 0 and args.workload == "simulation" else None)
     line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     print(json.dumps(line), flush=True)
 
