@@ -707,9 +707,17 @@ __device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt
 
 // One level of one query, run by the whole block: check every box, accumulate,
 // and write the admitted children of non-terminal colliding boxes.  PR / PW:
-// the level / the next level is stored packed.  Returns the block-reduced,
-// wave-uniform accumulator with keys as (t, u, v) indices, and the next
-// level's size.
+// the level / the next level is stored packed.  S and L are wave-uniform.
+// Returns the block-reduced, wave-uniform accumulator with keys as (t, u, v)
+// indices, and the next level's size.
+//
+// Children: the split axis field of a box gains one low bit (0: lower half,
+// 1: upper half).  In a packed key whose split field starts at bit sx this is
+//   child_b = ((key >> sx) << (sx + 1)) | (b << sx) | (key & (2^sx - 1)).
+// Child 0 shares the parent's (u_lo, v_lo), which passed the vertex-face prism
+// test when the parent was made (the root trivially), so only child 1 of a u or
+// v split is tested: u_lo + v_lo <= 1 with the new lower end, computed exactly
+// in binary64 (all values are multiples of 2^-52 below 2).
 template <int W, int KIND, bool PR, bool PW>
 __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
                                            int64_t cap, const State& S, const LevelInfo& L,
@@ -719,11 +727,12 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    KeyCodec kc, cc;
+    KeyCodec kc;
     kc.init(S.d[1], S.d[2]);
-    int cd[3] = {S.d[0], S.d[1], S.d[2]};
-    cd[L.axis] += 1;
-    cc.init(cd[1], cd[2]);
+    const int axis = L.axis;
+    const int sx = axis == 0 ? kc.st : (axis == 1 ? kc.su : 0);  // < 64 when PW
+    const uint64_t lowx = mask64(sx);
+    const double half_u = 0.5 * L.wu, half_v = 0.5 * L.wv;
     acc_init(A);
     unsigned long long next_w = 0;  // W == 1: running size of the next level
     if (W > 1) {
@@ -750,7 +759,6 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
             if (!PR) { p1 = ct[cap + inx]; p2 = ct[2 * cap + inx]; }
         }
         bool e0 = false, e1 = false;
-        uint64_t ch[2][3];
         if (act) {
             const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
             const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
@@ -761,11 +769,12 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
                 const bool term = R.small || L.dcap;
                 if (PR) acc_add_packed(A, key, bt, term, R.small, cap_level);
                 else acc_add(A, bt, bu, bv, term, R.small, cap_level);
-                if (!term) {
-                    bool ok[2];
-                    children(KIND, S, L, bt, bu, bv, ch, ok);
-                    e0 = ok[0];
-                    e1 = ok[1];
+                e0 = !term;
+                e1 = !term;
+                if (KIND == kVF && axis != 0) {
+                    const double cu = axis == 1 ? u0 + half_u : u0;
+                    const double cv = axis == 2 ? v0 + half_v : v0;
+                    e1 = e1 && (cu + cv <= 1.0);
                 }
             }
         }
@@ -784,11 +793,19 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         const int64_t q0 = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
         const int64_t q1 = q0 + (e0 ? 1 : 0);
         if (PW) {
-            if (e0 && q0 < cap) nt[q0] = cc.encode(ch[0][0], ch[0][1], ch[0][2]);
-            if (e1 && q1 < cap) nt[q1] = cc.encode(ch[1][0], ch[1][1], ch[1][2]);
+            const uint64_t c0 = (((key >> sx) << 1) << sx) | (key & lowx);
+            if (e0 && q0 < cap) nt[q0] = c0;
+            if (e1 && q1 < cap) nt[q1] = c0 | (1ull << sx);
         } else {
-            if (e0 && q0 < cap) { nt[q0] = ch[0][0]; nt[cap + q0] = ch[0][1]; nt[2 * cap + q0] = ch[0][2]; }
-            if (e1 && q1 < cap) { nt[q1] = ch[1][0]; nt[cap + q1] = ch[1][1]; nt[2 * cap + q1] = ch[1][2]; }
+            const uint64_t c0t = axis == 0 ? 2 * bt : bt;
+            const uint64_t c0u = axis == 1 ? 2 * bu : bu;
+            const uint64_t c0v = axis == 2 ? 2 * bv : bv;
+            if (e0 && q0 < cap) { nt[q0] = c0t; nt[cap + q0] = c0u; nt[2 * cap + q0] = c0v; }
+            if (e1 && q1 < cap) {
+                nt[q1] = c0t | (axis == 0 ? 1 : 0);
+                nt[cap + q1] = c0u | (axis == 1 ? 1 : 0);
+                nt[2 * cap + q1] = c0v | (axis == 2 ? 1 : 0);
+            }
         }
     }
     wave_reduce_acc(A);
@@ -943,14 +960,22 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         const int64_t r = uni64s(sh.rec);
         if (r >= in_count) break;
         const uint64_t* rec = g.in_records + r * g.in_record_words;
-        const Record h = *reinterpret_cast<const Record*>(rec);
+        // everything below is per query, hence wave-uniform (scalar registers)
+        Record h = *reinterpret_cast<const Record*>(rec);
+        h.q = uni64s(h.q);
+        h.N = uni64(h.N);
+        h.tpend = unif64(h.tpend);
+        h.wpend = unif64(h.wpend);
+        h.level = (int32_t)uni32((uint32_t)h.level);
+        for (int k = 0; k < 3; ++k) h.d[k] = (int32_t)uni32((uint32_t)h.d[k]);
+        h.cnt = uni32(h.cnt);
         const QView qv = view(a, h.q);
         const int64_t q = qv.q;
-        const int kind = qv.kind ? (int)qv.kind[q] : (int)qv.default_kind;
-        const double delta = qv.delta_q ? qv.delta_q[q] : qv.delta;
-        const int64_t max_iter = qv.max_iter_q ? qv.max_iter_q[q] : qv.max_iter;
-        const double min_sep = qv.min_sep_q ? qv.min_sep_q[q] : qv.min_sep;
-        const bool literal = (qv.flags & kFlagLiteral) != 0;
+        const int kind = (int)uni32(qv.kind ? (uint32_t)qv.kind[q] : qv.default_kind);
+        const double delta = unif64(qv.delta_q ? qv.delta_q[q] : qv.delta);
+        const int64_t max_iter = uni64s(qv.max_iter_q ? qv.max_iter_q[q] : qv.max_iter);
+        const double min_sep = unif64(qv.min_sep_q ? qv.min_sep_q[q] : qv.min_sep);
+        const bool literal = (uni32(qv.flags) & kFlagLiteral) != 0;
         if (tid < 24) {
             const int c = tid % 3, k = tid / 3;
             sh.Xs[c * 8 + k] = qv.pos[(int64_t)tid * qv.n + q];
@@ -979,6 +1004,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         double kappa[3];
         if (kind == kEE) kappa_lds<kEE>(sh.Xs, kappa);
         else kappa_lds<kVF>(sh.Xs, kappa);
+        for (int k = 0; k < 3; ++k) kappa[k] = unif64(kappa[k]);
         __syncthreads();
         if (kind == kEE)
             group_query<W, kEE>(a, g, sh, base, h, kappa, delta, min_sep, max_iter, literal, nchk[1], slots);
