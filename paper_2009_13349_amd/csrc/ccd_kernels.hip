@@ -62,6 +62,7 @@ struct Acc {
     uint32_t mhave;
     uint64_t tm;          // smallest it among terminal colliding boxes
     uint32_t thave;
+    int64_t fpos;         // group engine: where child 0 of the smallest key went, or -1
 };
 
 struct Outcome {
@@ -162,15 +163,17 @@ __device__ __forceinline__ void acc_init(Acc& A) {
     A.mhave = 0;
     A.tm = ~0ull;
     A.thave = 0;
+    A.fpos = -1;
 }
 
 // track_max: the largest colliding key is only needed on a level where the
 // m_I stop can fire (N + |level| >= m_I), a level-uniform condition.
 __device__ __forceinline__ void acc_add(Acc& A, uint64_t bt, uint64_t bu, uint64_t bv, bool term,
-                                        bool small, bool track_max = true) {
+                                        bool small, bool track_max = true, int64_t pos0 = -1) {
     if (!(A.fflags & 1u) || key_less(bt, bu, bv, A.ft, A.fu, A.fv)) {
         A.ft = bt; A.fu = bu; A.fv = bv;
         A.fflags = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
+        A.fpos = pos0;
     }
     if (track_max && (!A.mhave || key_less(A.mt, A.mu, A.mv, bt, bu, bv))) {
         A.mt = bt; A.mu = bu; A.mv = bv;
@@ -185,7 +188,7 @@ __device__ __forceinline__ void acc_add(Acc& A, uint64_t bt, uint64_t bu, uint64
 // Merge of two partial accumulators of the same level (commutative).
 __device__ __forceinline__ void acc_merge(Acc& A, const Acc& B) {
     if ((B.fflags & 1u) && (!(A.fflags & 1u) || key_less(B.ft, B.fu, B.fv, A.ft, A.fu, A.fv))) {
-        A.ft = B.ft; A.fu = B.fu; A.fv = B.fv; A.fflags = B.fflags;
+        A.ft = B.ft; A.fu = B.fu; A.fv = B.fv; A.fflags = B.fflags; A.fpos = B.fpos;
     }
     if (B.mhave && (!A.mhave || key_less(A.mt, A.mu, A.mv, B.mt, B.mu, B.mv))) {
         A.mt = B.mt; A.mu = B.mu; A.mv = B.mv; A.mhave = 1;
@@ -203,6 +206,33 @@ __device__ __forceinline__ bool need_rank(const Acc& A, const State& S, bool lit
     const bool carry_ret = !literal && S.tpend <= tf;
     const bool cap_possible = S.N + S.cnt >= (uint64_t)max_iter;
     return carry_ret || cap_possible || (A.fflags & 2u);
+}
+
+// The outcomes of a level that depend only on its first colliding box f (A
+// holds f as (t, u, v) indices) and rf, the number of the level's keys below
+// f: the carried box comes first, m_I is reached at f, or f is terminal.
+__device__ __forceinline__ Outcome decide_first(const Acc& A, const State& S, bool literal,
+                                                int64_t max_iter, const LevelInfo& L, uint64_t rf) {
+    Outcome O;
+    O.finish = true;
+    const uint64_t mI = (uint64_t)max_iter;
+    const double tf = (double)A.ft * L.wt;
+    const bool cap_possible = S.N + S.cnt >= mI;
+    const uint64_t nf = S.N + rf + 1;
+    if (!literal && S.tpend <= tf) {
+        O.toi = S.tpend; O.tw = S.wpend; O.n = nf < mI ? nf : mI; O.st = kStCarry;
+        return O;
+    }
+    if (cap_possible && nf >= mI) {
+        O.toi = tf; O.tw = L.wt; O.n = mI; O.st = kStCap;
+        return O;
+    }
+    if (A.fflags & 2u) {
+        O.toi = tf; O.tw = L.wt; O.n = nf; O.st = (A.fflags & 4u) ? 0 : kStDepth;
+        return O;
+    }
+    O.finish = false;
+    return O;
 }
 
 // The level's decision (Alg. 2 replayed over one level).  rf / rm: number of
@@ -225,21 +255,11 @@ __device__ __forceinline__ Outcome decide(const Acc& A, const State& S, bool lit
         }
         return O;
     }
+    O = decide_first(A, S, literal, max_iter, L, rf);
+    if (O.finish) return O;
     const double tf = (double)A.ft * L.wt;
     const bool cap_possible = S.N + S.cnt >= mI;
-    const uint64_t nf = S.N + rf + 1;
-    if (!literal && S.tpend <= tf) {
-        O.toi = S.tpend; O.tw = S.wpend; O.n = nf < mI ? nf : mI; O.st = kStCarry;
-        return O;
-    }
-    if (cap_possible && nf >= mI) {
-        O.toi = tf; O.tw = L.wt; O.n = mI; O.st = kStCap;
-        return O;
-    }
-    if (A.fflags & 2u) {
-        O.toi = tf; O.tw = L.wt; O.n = nf; O.st = (A.fflags & 4u) ? 0 : kStDepth;
-        return O;
-    }
+    O.finish = true;
     if (cap_possible && S.N + rm + 1 >= mI) {
         O.toi = tf; O.tw = L.wt; O.n = mI; O.st = kStCap;
         return O;
@@ -405,6 +425,7 @@ __device__ __forceinline__ void acc_uniform(Acc& A) {
     A.ft = uni64(A.ft); A.fu = uni64(A.fu); A.fv = uni64(A.fv); A.fflags = uni32(A.fflags);
     A.mt = uni64(A.mt); A.mu = uni64(A.mu); A.mv = uni64(A.mv); A.mhave = uni32(A.mhave);
     A.tm = uni64(A.tm); A.thave = uni32(A.thave);
+    A.fpos = uni64s(A.fpos);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,6 +654,7 @@ __device__ __forceinline__ void shfl_acc(Acc& B, const Acc& A, int off) {
     B.mhave = __shfl_xor(A.mhave, off);
     B.tm = __shfl_xor(A.tm, off);
     B.thave = __shfl_xor(A.thave, off);
+    B.fpos = __shfl_xor(A.fpos, off);
 }
 
 __device__ __forceinline__ void wave_reduce_acc(Acc& A) {
@@ -652,6 +674,7 @@ struct GroupShared {
     unsigned long long sum[W][2];
     unsigned long long next_cnt;
     int64_t rec;
+    uint64_t cand[64];  // head try: unchecked boxes below the running first colliding key
 };
 
 // ---------------------------------------------------------------------------
@@ -686,12 +709,13 @@ struct KeyCodec {
 
 // Accumulation with single-word keys (packed levels).
 __device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt, bool term,
-                                               bool small, bool track_max) {
+                                               bool small, bool track_max, int64_t pos0) {
     if (!(A.fflags & 1u) || key < A.ft) {
         A.ft = key;
         A.fu = 0;
         A.fv = 0;
         A.fflags = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
+        A.fpos = pos0;
     }
     if (track_max && (!A.mhave || A.mt < key)) {
         A.mt = key;
@@ -709,7 +733,8 @@ __device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt
 // and write the admitted children of non-terminal colliding boxes.  PR / PW:
 // the level / the next level is stored packed.  S and L are wave-uniform.
 // Returns the block-reduced, wave-uniform accumulator with keys as (t, u, v)
-// indices, and the next level's size.
+// indices, and the next level's size.  A.fpos is where child 0 of the
+// smallest colliding box was written.
 //
 // Children: the split axis field of a box gains one low bit (0: lower half,
 // 1: upper half).  In a packed key whose split field starts at bit sx this is
@@ -718,12 +743,25 @@ __device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt
 // test when the parent was made (the root trivially), so only child 1 of a u or
 // v split is tested: u_lo + v_lo <= 1 with the new lower end, computed exactly
 // in binary64 (all values are multiples of 2^-52 below 2).
+//
+// Head try (one wavefront, packed keys): Alg. 2 ends a level at its first
+// colliding box f when f is terminal, when the carried box comes first or when
+// m_I is reached at f; the boxes after f are never checked.  The first time a
+// chunk holds a colliding box for which one of these can hold, the running
+// smallest colliding key g is reduced and the unchecked boxes with keys below
+// g (usually none or few: the level's smallest key is stored first) are
+// checked from LDS.  f is then known exactly (every key below it has been
+// checked), its rank comes from a count, and if decide_first() ends the query
+// the pass returns early with that outcome; otherwise it goes on unchanged.
 template <int W, int KIND, bool PR, bool PW>
 __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
                                            int64_t cap, const State& S, const LevelInfo& L,
                                            double min_sep, double delta, bool cap_level,
-                                           Acc& A, uint64_t& next_cnt) {
+                                           bool literal, int64_t max_iter, Acc& A,
+                                           uint64_t& next_cnt, bool& early, Outcome& Oe,
+                                           uint64_t& checked) {
     constexpr int T = 64 * W;
+    constexpr bool kHead = (W == 1) && PR;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
@@ -734,12 +772,15 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
     const uint64_t lowx = mask64(sx);
     const double half_u = 0.5 * L.wu, half_v = 0.5 * L.wv;
     acc_init(A);
+    early = false;
+    bool tried = !kHead;
     unsigned long long next_w = 0;  // W == 1: running size of the next level
     if (W > 1) {
         if (tid == 0) sh.next_cnt = 0;
         __syncthreads();
     }
     const int64_t cnt = S.cnt;
+    checked = (uint64_t)cnt;
     // software pipelining: the next chunk's boxes load while this one computes
     uint64_t p0 = 0, p1 = 0, p2 = 0;
     if (tid < cnt) {
@@ -758,24 +799,24 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
             p0 = ct[inx];
             if (!PR) { p1 = ct[cap + inx]; p2 = ct[2 * cap + inx]; }
         }
+        bool col = false, term = false, small = false;
         bool e0 = false, e1 = false;
+        double t0 = 0.0;
         if (act) {
-            const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
+            t0 = dyadic(bt, L.bt_bits, L.bt_val);
             const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
             const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
             const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, t0, t0 + L.wt, u0, u0 + L.wu,
                                                       v0, v0 + L.wv, min_sep, delta);
-            if (R.collide) {
-                const bool term = R.small || L.dcap;
-                if (PR) acc_add_packed(A, key, bt, term, R.small, cap_level);
-                else acc_add(A, bt, bu, bv, term, R.small, cap_level);
-                e0 = !term;
-                e1 = !term;
-                if (KIND == kVF && axis != 0) {
-                    const double cu = axis == 1 ? u0 + half_u : u0;
-                    const double cv = axis == 2 ? v0 + half_v : v0;
-                    e1 = e1 && (cu + cv <= 1.0);
-                }
+            col = R.collide;
+            small = R.small;
+            term = R.small || L.dcap;
+            e0 = col && !term;
+            e1 = e0;
+            if (KIND == kVF && axis != 0) {
+                const double cu = axis == 1 ? u0 + half_u : u0;
+                const double cv = axis == 2 ? v0 + half_v : v0;
+                e1 = e1 && (cu + cv <= 1.0);
             }
         }
         const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
@@ -792,6 +833,11 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         const uint64_t lt = lanemask_lt();
         const int64_t q0 = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
         const int64_t q1 = q0 + (e0 ? 1 : 0);
+        if (col) {
+            const int64_t pos0 = (e0 && q0 < cap) ? q0 : -1;
+            if (PR) acc_add_packed(A, key, bt, term, small, cap_level, pos0);
+            else acc_add(A, bt, bu, bv, term, small, cap_level, pos0);
+        }
         if (PW) {
             const uint64_t c0 = (((key >> sx) << 1) << sx) | (key & lowx);
             if (e0 && q0 < cap) nt[q0] = c0;
@@ -805,6 +851,71 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
                 nt[q1] = c0t | (axis == 0 ? 1 : 0);
                 nt[cap + q1] = c0u | (axis == 1 ? 1 : 0);
                 nt[2 * cap + q1] = c0v | (axis == 2 ? 1 : 0);
+            }
+        }
+        if (kHead && !tried) {
+            const bool ends = col && (term || cap_level || (!literal && S.tpend <= t0));
+            if (__ballot(ends) != 0) {
+                tried = true;
+                Acc F = A;
+                wave_reduce_acc(F);
+                acc_uniform(F);
+                const uint64_t g = F.ft;  // packed
+                const int64_t done = b0 + T < cnt ? b0 + T : cnt;
+                // unchecked boxes with keys below g, gathered in LDS
+                uint32_t nc = 0;
+                bool fits = true;
+                for (int64_t j0 = done; j0 < cnt; j0 += T) {
+                    const int64_t j = j0 + lane;
+                    const uint64_t k = j < cnt ? ct[j] : ~0ull;
+                    const bool below = j < cnt && k < g;
+                    const uint64_t m = __ballot(below);
+                    if (m) {
+                        const uint32_t c = (uint32_t)__popcll(m);
+                        if (nc + c > 64) { fits = false; break; }
+                        if (below) sh.cand[nc + __popcll(m & lt)] = k;
+                        nc += c;
+                    }
+                }
+                if (fits) {
+                    __syncthreads();  // one wavefront: orders the LDS writes before the reads
+                    Acc C;
+                    acc_init(C);
+                    uint64_t ck = ~0ull;
+                    if ((uint32_t)lane < nc) {
+                        ck = sh.cand[lane];
+                        uint64_t xt, xu, xv;
+                        kc.decode(ck, xt, xu, xv);
+                        const double x0 = dyadic(xt, L.bt_bits, L.bt_val);
+                        const double y0 = dyadic(xu, L.bu_bits, L.bu_val);
+                        const double z0 = dyadic(xv, L.bv_bits, L.bv_val);
+                        const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, x0, x0 + L.wt, y0,
+                                                                  y0 + L.wu, z0, z0 + L.wv,
+                                                                  min_sep, delta);
+                        if (R.collide)
+                            acc_add_packed(C, ck, xt, R.small || L.dcap, R.small, false, -1);
+                    }
+                    wave_reduce_acc(C);
+                    acc_uniform(C);
+                    acc_merge(F, C);
+                    const uint64_t f = F.ft;  // the level's first colliding key
+                    // rank of f: checked chunks plus gathered candidates
+                    unsigned long long r = ck < f ? 1 : 0;
+                    for (int64_t j = lane; j < done; j += T) r += ct[j] < f ? 1 : 0;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+                    const uint64_t rf = uni64(r);
+                    uint64_t ft, fu, fv;
+                    kc.decode(f, ft, fu, fv);
+                    F.ft = ft; F.fu = fu; F.fv = fv;
+                    const Outcome O = decide_first(F, S, literal, max_iter, L, rf);
+                    if (O.finish) {
+                        early = true;
+                        Oe = O;
+                        checked = (uint64_t)done + nc;
+                        return;
+                    }
+                }
             }
         }
     }
@@ -891,16 +1002,25 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
         const bool pw = depth_sum(S.d) + 1 <= 64;
         const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
         Acc A;
-        uint64_t next_cnt;
+        uint64_t next_cnt = 0, checked = 0;
+        bool early;
+        Outcome Oe;
         if (pw)
-            level_pass<W, KIND, true, true>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+            level_pass<W, KIND, true, true>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, literal,
+                                            max_iter, A, next_cnt, early, Oe, checked);
         else if (pr)
-            level_pass<W, KIND, true, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+            level_pass<W, KIND, true, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, literal,
+                                             max_iter, A, next_cnt, early, Oe, checked);
         else
-            level_pass<W, KIND, false, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, A, next_cnt);
+            level_pass<W, KIND, false, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level,
+                                              literal, max_iter, A, next_cnt, early, Oe, checked);
         if (tid == 0) {
-            nchk += (uint64_t)S.cnt;
-            slots += (uint64_t)((S.cnt + T - 1) / T) * T;
+            nchk += checked;
+            slots += (uint64_t)((checked + T - 1) / T) * T;
+        }
+        if (early) {
+            if (tid == 0) write_result(a, h.q, Oe);
+            return;
         }
         uint64_t rf = 0, rm = 0;
         if (need_rank(A, S, literal, max_iter, L)) {
@@ -934,6 +1054,21 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
                 if (!placed) atomicAdd(&a.counters[kCntError], 1ull);
             }
             return;
+        }
+        // f is colliding and not terminal here, so its child 0 is on the next
+        // level, where it is the smallest key (Alg. 2 order is preserved by
+        // bisection): store it first, where the head try looks first
+        if (A.fpos > 0) {
+            __syncthreads();
+            if (tid == 0) {
+                const int64_t p = A.fpos;
+                const int words = pw ? 1 : 3;
+                for (int w = 0; w < words; ++w) {
+                    const uint64_t x0 = nt[w * cap], xp = nt[w * cap + p];
+                    nt[w * cap] = xp;
+                    nt[w * cap + p] = x0;
+                }
+            }
         }
         advance(S, A, literal, L, (uint32_t)next_cnt);
         cur ^= 1;

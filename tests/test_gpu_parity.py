@@ -181,6 +181,81 @@ def test_results_independent_of_tuning_and_engine(ctx, torch_dev):
             assert_same(got, ref, what=f"tuning {tune} engine {engine}")
 
 
+def _hard_queries(count, seed):
+    """Simulation-shaped queries whose sequential run takes more than 256
+    checks (the ones the wide engines solve), chosen with the oracle."""
+    w = W.simulation_mixed(20_000, seed=seed)
+    ref = run_oracle(w, max_iter=1_000_000)
+    idx = np.nonzero(ref["n_checks"] > 256)[0]
+    vf = idx[w["kind"][idx] == 0][: count // 2]
+    ee = idx[w["kind"][idx] == 1][: count - len(vf)]
+    return W.subset(w, np.concatenate([vf, ee]))
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_group_engine_every_small_cap(ctx, torch_dev, literal):
+    """Hard queries forced into the group engines at every m_I from 1 to 600:
+    the m_I stop lands on every position of the early levels, including the
+    leading box of a level (the group engine's stop after one chunk) and the
+    carried box (default mode)."""
+    h = _hard_queries(8, seed=21)
+    k = h["pos"].shape[1]
+    caps = np.arange(1, 601, dtype=np.int64)
+    w = W.subset(h, np.repeat(np.arange(k), len(caps)))
+    mq = np.tile(caps, k)
+    ref = run_oracle(w, max_iter_q=mq, literal=literal)
+    for tune in ({"lane_capacity": 8, "lane_budget": 1},
+                 {"lane_capacity": 8, "lane_budget": 1, "group_waves": 8}):
+        ctx.set_tuning(**tune)
+        got = run_gpu(ctx, torch_dev, w, 0, max_iter_q=mq, literal=literal)
+        assert_same(got, ref, what=f"caps 1..600 literal={literal} tuning {tune}")
+
+
+def test_group_engine_hard_queries(ctx, torch_dev):
+    """Hard queries to the end (m_I = 1e6), default and literal modes, through
+    the group engines with one- and eight-wave blocks."""
+    w = _hard_queries(200, seed=22)
+    for literal in (False, True):
+        ref = run_oracle(w, max_iter=1_000_000, literal=literal)
+        for tune in ({"lane_capacity": 8, "lane_budget": 1},
+                     {"lane_capacity": 8, "lane_budget": 1, "group_waves": 8},
+                     {"lane_capacity": 8, "lane_budget": 1, "group_capacity": 512}):
+            ctx.set_tuning(**tune)
+            got = run_gpu(ctx, torch_dev, w, 0, max_iter=1_000_000, literal=literal)
+            assert_same(got, ref, what=f"hard literal={literal} tuning {tune}")
+
+
+def test_group_engine_carried_returns(ctx, torch_dev):
+    """Queries that end on a carried terminal box (delta = 1e-2 makes boxes of
+    one level terminal at different depths), through the lane and group
+    engines, with m_I at and around each query's own check count."""
+    delta = 1e-2
+    parts = []
+    for w0 in (W.uniform_vf(20_000, seed=31), W.edge_edge_mixed(20_000, seed=33)):
+        r0 = run_oracle(w0, delta=delta)
+        parts.append(W.subset(w0, np.nonzero(r0["status"] & 2)[0]))
+    w = W.concat(parts)
+    k = w["pos"].shape[1]
+    assert k >= 100
+    r1 = run_oracle(w, delta=delta)
+    rng = np.random.default_rng(3)
+    offs = np.array([-3, -2, -1, 0, 1, 5], dtype=np.int64)
+    base = r1["n_checks"].astype(np.int64)
+    mq = np.concatenate([np.maximum(1, base + o) for o in offs] +
+                        [rng.integers(1, np.maximum(2, base))])
+    ww = W.subset(w, np.tile(np.arange(k), len(offs) + 1))
+    for literal in (False, True):
+        ref = run_oracle(ww, delta=delta, max_iter_q=mq, literal=literal)
+        if not literal:
+            assert np.count_nonzero(ref["status"] == 2) >= 50
+        for tune in ({}, {"lane_capacity": 8, "lane_budget": 1},
+                     {"lane_capacity": 8, "lane_budget": 1, "group_waves": 8}):
+            if tune:
+                ctx.set_tuning(**tune)
+            got = run_gpu(ctx, torch_dev, ww, 0, delta=delta, max_iter_q=mq, literal=literal)
+            assert_same(got, ref, what=f"carried returns literal={literal} tuning {tune}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 257, 1031])
 def test_ragged_sizes(ctx, torch_dev, n):
     w = W.concat([W.uniform_vf(n, seed=13), W.edge_edge_mixed(n, seed=14)])
