@@ -666,16 +666,6 @@ __device__ __forceinline__ void wave_reduce_acc(Acc& A) {
     }
 }
 
-template <int W>
-struct GroupShared {
-    double Xs[24];  // the query's coordinates, Xs[c*8 + k]
-    double Es[3];   // eps per axis
-    Acc acc[W];
-    unsigned long long sum[W][2];
-    unsigned long long next_cnt;
-    int64_t rec;
-    uint64_t cand[64];  // head try: unchecked boxes below the running first colliding key
-};
 
 // ---------------------------------------------------------------------------
 // Frontier encodings of the group engine.  A level whose total bisection depth
@@ -707,34 +697,184 @@ struct KeyCodec {
     }
 };
 
-// Accumulation with single-word keys (packed levels).
-__device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt, bool term,
-                                               bool small, bool track_max, int64_t pos0) {
-    if (!(A.fflags & 1u) || key < A.ft) {
-        A.ft = key;
-        A.fu = 0;
-        A.fv = 0;
-        A.fflags = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
-        A.fpos = pos0;
+// Accumulator of a packed level: keys are single words.
+struct KeyAcc {
+    uint64_t f;      // smallest colliding key
+    uint64_t m;      // largest colliding key (levels where m_I can stop)
+    uint64_t tm;     // smallest it among terminal colliding boxes
+    int64_t fpos;    // where child 0 of f went, or -1
+    uint32_t ff;     // bit0: have, bit1: terminal, bit2: small
+    uint32_t mh;
+    uint32_t th;
+};
+
+__device__ __forceinline__ void keyacc_init(KeyAcc& K) {
+    K.f = ~0ull; K.m = 0; K.tm = ~0ull; K.fpos = -1; K.ff = 0; K.mh = 0; K.th = 0;
+}
+
+__device__ __forceinline__ void keyacc_add(KeyAcc& K, uint64_t key, uint64_t bt, bool term,
+                                           bool small, bool track_max, int64_t pos0) {
+    if (!(K.ff & 1u) || key < K.f) {
+        K.f = key;
+        K.ff = 1u | (term ? 2u : 0u) | (small ? 4u : 0u);
+        K.fpos = pos0;
     }
-    if (track_max && (!A.mhave || A.mt < key)) {
-        A.mt = key;
-        A.mu = 0;
-        A.mv = 0;
-        A.mhave = 1;
+    if (track_max && (!K.mh || K.m < key)) {
+        K.m = key;
+        K.mh = 1;
     }
-    if (term && (!A.thave || bt < A.tm)) {
-        A.tm = bt;
-        A.thave = 1;
+    if (term && (!K.th || bt < K.tm)) {
+        K.tm = bt;
+        K.th = 1;
     }
 }
 
+__device__ __forceinline__ void keyacc_merge(KeyAcc& K, const KeyAcc& B) {
+    if ((B.ff & 1u) && (!(K.ff & 1u) || B.f < K.f)) { K.f = B.f; K.ff = B.ff; K.fpos = B.fpos; }
+    if (B.mh && (!K.mh || K.m < B.m)) { K.m = B.m; K.mh = 1; }
+    if (B.th && (!K.th || B.tm < K.tm)) { K.tm = B.tm; K.th = 1; }
+}
+
+// Wavefront reduction; the result is made wave-uniform.
+__device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        KeyAcc B;
+        B.f = __shfl_xor(K.f, off); B.m = __shfl_xor(K.m, off); B.tm = __shfl_xor(K.tm, off);
+        B.fpos = __shfl_xor(K.fpos, off); B.ff = __shfl_xor(K.ff, off);
+        B.mh = __shfl_xor(K.mh, off); B.th = __shfl_xor(K.th, off);
+        keyacc_merge(K, B);
+    }
+    K.f = uni64(K.f); K.m = uni64(K.m); K.tm = uni64(K.tm); K.fpos = uni64s(K.fpos);
+    K.ff = uni32(K.ff); K.mh = uni32(K.mh); K.th = uni32(K.th);
+}
+
+// Storage formats of a level in a group arena buffer.
+constexpr int kFmtKey = 0;     // one packed key per box (depth sum <= 64)
+constexpr int kFmtPair = 1;    // one word per sibling pair: parent key | flag << 63
+constexpr int kFmtTriple = 2;  // (it, iu, iv) in three arrays, any depth
+constexpr uint64_t kPairFlag = 1ull << 63;  // the pair's child 1 passed the prism test
+
+template <int W>
+struct GroupShared {
+    double Xs[24];  // the query's coordinates, Xs[c*8 + k]
+    double Es[3];   // eps per axis
+    Acc acc[W];
+    KeyAcc kacc[W];
+    unsigned long long sum[W][2];
+    unsigned long long next_cnt;  // W > 1: words of the next level
+    unsigned long long next_box;  // W > 1: boxes of the next level
+    int64_t rec;
+    uint64_t cand[64];  // head try: unchecked words below the running first colliding key
+};
+
+// ---------------------------------------------------------------------------
+// Sibling pairs.  Alg. 2 checks both children of every colliding box that is
+// not terminal (the second one only if the vertex-face prism test admits it).
+// The two children share the face of the split: 4 of their 8 corners and, on
+// a u or v split, both t planes.  A level stored as pairs is checked a pair per
+// lane with the shared corner values computed once; every corner value is the
+// same sequence of binary64 operations as corner_values_axis() for that
+// corner, so the results are those of checking the two boxes one by one.
+//
+// tv, uv, vv: the box's lower and upper ends per axis; on the split axis SPLIT
+// three values lo < mid < hi (child 0 = [lo, mid], child 1 = [mid, hi]).
+template <int KIND, int SPLIT>
+__device__ __forceinline__ void check_pair_lds(const double* Xs, const double* Es,
+                                               const double tv[3], const double uv[3],
+                                               const double vv[3], double min_sep, double delta,
+                                               bool act1, CheckResult& R0, CheckResult& R1) {
+    constexpr int NA = SPLIT == 0 ? 3 : 2;
+    constexpr int NB = SPLIT == 1 ? 3 : 2;
+    constexpr int NE = SPLIT == 2 ? 3 : 2;
+    bool col0 = true, ins0 = true, col1 = act1, ins1 = true;
+    double wid0 = 0.0, wid1 = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        if (__ballot(col0 || col1) == 0) break;
+        const double* xs = Xs + c * 8;
+        double lo0 = INFINITY, hi0 = -INFINITY, lo1 = INFINITY, hi1 = -INFINITY;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const double ta = tv[a];
+            const double sa = 1.0 - ta;
+            double P[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) P[k] = sa * xs[k] + ta * xs[k + 4];
+            double ea[NB], eb[NE];
+            if (KIND == kEE) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) ea[b] = (1.0 - uv[b]) * P[0] + uv[b] * P[1];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) eb[e] = (1.0 - vv[e]) * P[2] + vv[e] * P[3];
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    double f;
+                    if (KIND == kEE) {
+                        f = ea[b] - eb[e];
+                    } else {
+                        const double w = (1.0 - uv[b]) - vv[e];
+                        const double s12 = w * P[1] + uv[b] * P[2];
+                        f = P[0] - (s12 + vv[e] * P[3]);
+                    }
+                    const int sp = SPLIT == 0 ? a : (SPLIT == 1 ? b : e);
+                    if (sp <= 1) { lo0 = fmin(lo0, f); hi0 = fmax(hi0, f); }
+                    if (sp >= 1) { lo1 = fmin(lo1, f); hi1 = fmax(hi1, f); }
+                }
+        }
+        const double eps = Es[c];
+        {
+            const double l = lo0 - min_sep, h = hi0 + min_sep;
+            col0 = col0 && (l <= eps) && (h >= -eps);
+            ins0 = ins0 && (l >= -eps) && (h <= eps);
+            wid0 = fmax(wid0, hi0 - lo0);
+        }
+        {
+            const double l = lo1 - min_sep, h = hi1 + min_sep;
+            col1 = col1 && (l <= eps) && (h >= -eps);
+            ins1 = ins1 && (l >= -eps) && (h <= eps);
+            wid1 = fmax(wid1, hi1 - lo1);
+        }
+    }
+    R0.collide = col0;
+    R0.small = (wid0 < delta) || ins0;
+    R1.collide = col1;
+    R1.small = (wid1 < delta) || ins1;
+}
+
+// Child key b of a pair word's parent key (split field at bit sx of the
+// current level's packed key).
+__device__ __forceinline__ uint64_t pair_child(uint64_t word, int sx, uint64_t lowx, uint64_t b) {
+    const uint64_t pk = word & ~kPairFlag;
+    return ((((pk >> sx) << 1) | b) << sx) | (pk & lowx);
+}
+
+// Shift of an axis field in a packed key with depths (du, dv).
+__device__ __forceinline__ int field_shift(int axis, const KeyCodec& kc) {
+    return axis == 0 ? kc.st : (axis == 1 ? kc.su : 0);
+}
+
+// The boxes one lane holds in one chunk: one (Key / Triple input) or the two
+// siblings of a pair word.
+struct LaneBoxes {
+    uint64_t key[2];          // packed keys (Key / Pair input)
+    uint64_t it[2], iu[2], iv[2];
+    double t0[2], u0[2], v0[2];
+    bool act[2];
+    CheckResult R[2];
+};
+
 // One level of one query, run by the whole block: check every box, accumulate,
-// and write the admitted children of non-terminal colliding boxes.  PR / PW:
-// the level / the next level is stored packed.  S and L are wave-uniform.
+// and store what the next level needs.  FIN: this level's storage format;
+// SPLIT: for pair input, the axis the stored parents were split on; OP: store
+// the next level as pairs (each colliding box that is not terminal becomes one
+// word), else as triples (its admitted children).  S and L are wave-uniform.
 // Returns the block-reduced, wave-uniform accumulator with keys as (t, u, v)
-// indices, and the next level's size.  A.fpos is where child 0 of the
-// smallest colliding box was written.
+// indices, the next level's word and box counts, and in A.fpos where the word
+// (pairs) or child 0 (triples) of the smallest colliding box went.
 //
 // Children: the split axis field of a box gains one low bit (0: lower half,
 // 1: upper half).  In a packed key whose split field starts at bit sx this is
@@ -744,204 +884,306 @@ __device__ __forceinline__ void acc_add_packed(Acc& A, uint64_t key, uint64_t bt
 // v split is tested: u_lo + v_lo <= 1 with the new lower end, computed exactly
 // in binary64 (all values are multiples of 2^-52 below 2).
 //
-// Head try (one wavefront, packed keys): Alg. 2 ends a level at its first
+// Head try (one wavefront, packed input): Alg. 2 ends a level at its first
 // colliding box f when f is terminal, when the carried box comes first or when
 // m_I is reached at f; the boxes after f are never checked.  The first time a
 // chunk holds a colliding box for which one of these can hold, the running
-// smallest colliding key g is reduced and the unchecked boxes with keys below
-// g (usually none or few: the level's smallest key is stored first) are
+// smallest colliding key g is reduced and the unchecked words holding a key
+// below g (usually none or few: the level's smallest key is stored first) are
 // checked from LDS.  f is then known exactly (every key below it has been
 // checked), its rank comes from a count, and if decide_first() ends the query
 // the pass returns early with that outcome; otherwise it goes on unchanged.
-template <int W, int KIND, bool PR, bool PW>
+template <int W, int KIND, int FIN, int SPLIT, bool OP>
 __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
-                                           int64_t cap, const State& S, const LevelInfo& L,
-                                           double min_sep, double delta, bool cap_level,
-                                           bool literal, int64_t max_iter, Acc& A,
-                                           uint64_t& next_cnt, bool& early, Outcome& Oe,
-                                           uint64_t& checked) {
+                                           int64_t cap, const State& S, int64_t words,
+                                           const LevelInfo& L, double min_sep, double delta,
+                                           bool cap_level, bool literal, int64_t max_iter, Acc& A,
+                                           uint64_t& next_words, uint64_t& next_boxes,
+                                           bool& early, Outcome& Oe, uint64_t& checked) {
     constexpr int T = 64 * W;
-    constexpr bool kHead = (W == 1) && PR;
+    constexpr bool kPacked = FIN != kFmtTriple;
+    constexpr bool kPair = FIN == kFmtPair;
+    constexpr bool kHead = (W == 1) && kPacked;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     KeyCodec kc;
     kc.init(S.d[1], S.d[2]);
     const int axis = L.axis;
-    const int sx = axis == 0 ? kc.st : (axis == 1 ? kc.su : 0);  // < 64 when PW
+    const int sx = field_shift(axis, kc);  // < 64 when OP
     const uint64_t lowx = mask64(sx);
+    const int psx = kPair ? field_shift(SPLIT, kc) : 0;  // split field of the stored parents
+    const uint64_t plowx = mask64(psx);
     const double half_u = 0.5 * L.wu, half_v = 0.5 * L.wv;
-    acc_init(A);
+    const double wsp = SPLIT == 0 ? L.wt : (SPLIT == 1 ? L.wu : L.wv);
+    KeyAcc K;  // packed input
+    if (kPacked) keyacc_init(K);
+    else acc_init(A);
     early = false;
     bool tried = !kHead;
-    unsigned long long next_w = 0;  // W == 1: running size of the next level
+    uint64_t boxes_done = 0;
+    unsigned long long next_w = 0, next_b = 0;  // W == 1: running sizes of the next level
     if (W > 1) {
-        if (tid == 0) sh.next_cnt = 0;
+        if (tid == 0) { sh.next_cnt = 0; sh.next_box = 0; }
         __syncthreads();
     }
-    const int64_t cnt = S.cnt;
-    checked = (uint64_t)cnt;
-    // software pipelining: the next chunk's boxes load while this one computes
-    uint64_t p0 = 0, p1 = 0, p2 = 0;
-    if (tid < cnt) {
-        p0 = ct[tid];
-        if (!PR) { p1 = ct[cap + tid]; p2 = ct[2 * cap + tid]; }
-    }
-    for (int64_t b0 = 0; b0 < cnt; b0 += T) {
-        const int64_t i = b0 + tid;
-        const bool act = i < cnt;
-        uint64_t bt, bu, bv;
-        const uint64_t key = p0;
-        if (PR) kc.decode(key, bt, bu, bv);
-        else { bt = p0; bu = p1; bv = p2; }
-        const int64_t inx = i + T;
-        if (inx < cnt) {
-            p0 = ct[inx];
-            if (!PR) { p1 = ct[cap + inx]; p2 = ct[2 * cap + inx]; }
+
+    // the boxes of the word at index i (FIN's format) and their checks
+    auto load = [&](int64_t i, uint64_t& p0, uint64_t& p1, uint64_t& p2) {
+        p0 = ct[i];
+        if (!kPacked) { p1 = ct[cap + i]; p2 = ct[2 * cap + i]; }
+    };
+    auto expand = [&](bool act, uint64_t p0, uint64_t p1, uint64_t p2, LaneBoxes& B) {
+        B.act[0] = act;
+        B.act[1] = false;
+        if (kPair) {
+            B.key[0] = pair_child(p0, psx, plowx, 0);
+            B.key[1] = B.key[0] | (1ull << psx);
+            B.act[1] = act && (p0 & kPairFlag);
+            kc.decode(B.key[0], B.it[0], B.iu[0], B.iv[0]);
+            B.it[1] = B.it[0] + (SPLIT == 0 ? 1 : 0);
+            B.iu[1] = B.iu[0] + (SPLIT == 1 ? 1 : 0);
+            B.iv[1] = B.iv[0] + (SPLIT == 2 ? 1 : 0);
+        } else if (kPacked) {
+            B.key[0] = p0;
+            kc.decode(p0, B.it[0], B.iu[0], B.iv[0]);
+        } else {
+            B.it[0] = p0; B.iu[0] = p1; B.iv[0] = p2;
         }
-        bool col = false, term = false, small = false;
-        bool e0 = false, e1 = false;
-        double t0 = 0.0;
-        if (act) {
-            t0 = dyadic(bt, L.bt_bits, L.bt_val);
-            const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
-            const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
-            const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, t0, t0 + L.wt, u0, u0 + L.wu,
-                                                      v0, v0 + L.wv, min_sep, delta);
-            col = R.collide;
-            small = R.small;
-            term = R.small || L.dcap;
-            e0 = col && !term;
-            e1 = e0;
+        B.t0[0] = dyadic(B.it[0], L.bt_bits, L.bt_val);
+        B.u0[0] = dyadic(B.iu[0], L.bu_bits, L.bu_val);
+        B.v0[0] = dyadic(B.iv[0], L.bv_bits, L.bv_val);
+        if (kPair) {
+            B.t0[1] = SPLIT == 0 ? B.t0[0] + wsp : B.t0[0];
+            B.u0[1] = SPLIT == 1 ? B.u0[0] + wsp : B.u0[0];
+            B.v0[1] = SPLIT == 2 ? B.v0[0] + wsp : B.v0[0];
+        }
+    };
+    auto check = [&](LaneBoxes& B) {
+        B.R[0].collide = false; B.R[0].small = false;
+        B.R[1].collide = false; B.R[1].small = false;
+        if (!B.act[0]) return;
+        if (kPair) {
+            double tv[3], uv[3], vv[3];
+            tv[0] = B.t0[0]; tv[1] = tv[0] + L.wt; tv[2] = tv[1] + L.wt;
+            uv[0] = B.u0[0]; uv[1] = uv[0] + L.wu; uv[2] = uv[1] + L.wu;
+            vv[0] = B.v0[0]; vv[1] = vv[0] + L.wv; vv[2] = vv[1] + L.wv;
+            check_pair_lds<KIND, SPLIT>(sh.Xs, sh.Es, tv, uv, vv, min_sep, delta, B.act[1],
+                                        B.R[0], B.R[1]);
+        } else {
+            B.R[0] = check_box_lds<KIND>(sh.Xs, sh.Es, B.t0[0], B.t0[0] + L.wt, B.u0[0],
+                                         B.u0[0] + L.wu, B.v0[0], B.v0[0] + L.wv, min_sep, delta);
+        }
+    };
+
+    uint64_t p0 = 0, p1 = 0, p2 = 0;  // software pipelining: the next chunk loads early
+    if (tid < words) load(tid, p0, p1, p2);
+    for (int64_t b0 = 0; b0 < words; b0 += T) {
+        const int64_t i = b0 + tid;
+        const bool act = i < words;
+        LaneBoxes B;
+        expand(act, p0, p1, p2, B);
+        const int64_t inx = i + T;
+        if (inx < words) load(inx, p0, p1, p2);
+        check(B);
+        if (kHead) boxes_done += __popcll(__ballot(B.act[0])) + __popcll(__ballot(B.act[1]));
+        bool col[2], term[2], e[2], adm[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            col[b] = B.R[b].collide;
+            term[b] = B.R[b].small || L.dcap;
+            e[b] = col[b] && !term[b];
+            adm[b] = true;
             if (KIND == kVF && axis != 0) {
-                const double cu = axis == 1 ? u0 + half_u : u0;
-                const double cv = axis == 2 ? v0 + half_v : v0;
-                e1 = e1 && (cu + cv <= 1.0);
+                const double cu = axis == 1 ? B.u0[b] + half_u : B.u0[b];
+                const double cv = axis == 2 ? B.v0[b] + half_v : B.v0[b];
+                adm[b] = cu + cv <= 1.0;
             }
         }
-        const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
-        const unsigned long long tot = __popcll(m0) + __popcll(m1);
+        // positions of what this lane stores for the next level
+        const uint64_t lt = lanemask_lt();
+        int64_t q[2];
+        unsigned long long wtot, btot;
+        uint64_t mk[4];
+        if (OP) {
+            mk[0] = __ballot(e[0]); mk[1] = __ballot(e[1]);
+            mk[2] = __ballot(e[0] && adm[0]); mk[3] = __ballot(e[1] && adm[1]);
+            wtot = __popcll(mk[0]) + __popcll(mk[1]);
+            btot = wtot + __popcll(mk[2]) + __popcll(mk[3]);
+        } else {
+            mk[0] = __ballot(e[0]); mk[1] = __ballot(e[0] && adm[0]);
+            mk[2] = __ballot(e[1]); mk[3] = __ballot(e[1] && adm[1]);
+            wtot = __popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]) + __popcll(mk[3]);
+            btot = wtot;
+        }
         unsigned long long wbase;
         if (W == 1) {
             wbase = next_w;
-            next_w += tot;
+            next_w += wtot;
+            next_b += btot;
         } else {
             unsigned long long t = 0;
-            if (lane == 0 && tot) t = atomicAdd(&sh.next_cnt, tot);
+            if (lane == 0 && wtot) {
+                t = atomicAdd(&sh.next_cnt, wtot);
+                atomicAdd(&sh.next_box, btot);
+            }
             wbase = uni64(__shfl(t, 0));
         }
-        const uint64_t lt = lanemask_lt();
-        const int64_t q0 = (int64_t)wbase + __popcll(m0 & lt) + __popcll(m1 & lt);
-        const int64_t q1 = q0 + (e0 ? 1 : 0);
-        if (col) {
-            const int64_t pos0 = (e0 && q0 < cap) ? q0 : -1;
-            if (PR) acc_add_packed(A, key, bt, term, small, cap_level, pos0);
-            else acc_add(A, bt, bu, bv, term, small, cap_level, pos0);
-        }
-        if (PW) {
-            const uint64_t c0 = (((key >> sx) << 1) << sx) | (key & lowx);
-            if (e0 && q0 < cap) nt[q0] = c0;
-            if (e1 && q1 < cap) nt[q1] = c0 | (1ull << sx);
+        if (OP) {
+            // one word per stored box; mk[2], mk[3] only count boxes
+            q[0] = (int64_t)wbase + __popcll(mk[0] & lt) + __popcll(mk[1] & lt);
+            q[1] = q[0] + (e[0] ? 1 : 0);
         } else {
-            const uint64_t c0t = axis == 0 ? 2 * bt : bt;
-            const uint64_t c0u = axis == 1 ? 2 * bu : bu;
-            const uint64_t c0v = axis == 2 ? 2 * bv : bv;
-            if (e0 && q0 < cap) { nt[q0] = c0t; nt[cap + q0] = c0u; nt[2 * cap + q0] = c0v; }
-            if (e1 && q1 < cap) {
-                nt[q1] = c0t | (axis == 0 ? 1 : 0);
-                nt[cap + q1] = c0u | (axis == 1 ? 1 : 0);
-                nt[2 * cap + q1] = c0v | (axis == 2 ? 1 : 0);
+            // up to four child triples per lane, all counted by mk[0..3]
+            int64_t o = (int64_t)wbase;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o += __popcll(mk[j] & lt);
+            q[0] = o;
+            q[1] = o + (e[0] ? 1 : 0) + (e[0] && adm[0] ? 1 : 0);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (!col[b]) continue;
+            const int64_t pos = (e[b] && q[b] < cap) ? q[b] : -1;
+            if (kPacked) keyacc_add(K, B.key[b], B.it[b], term[b], B.R[b].small, cap_level, pos);
+            else acc_add(A, B.it[b], B.iu[b], B.iv[b], term[b], B.R[b].small, cap_level, pos);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (!e[b]) continue;
+            if (OP) {
+                if (q[b] < cap) nt[q[b]] = B.key[b] | (adm[b] ? kPairFlag : 0ull);
+            } else {
+                const uint64_t c0t = axis == 0 ? 2 * B.it[b] : B.it[b];
+                const uint64_t c0u = axis == 1 ? 2 * B.iu[b] : B.iu[b];
+                const uint64_t c0v = axis == 2 ? 2 * B.iv[b] : B.iv[b];
+                const int64_t r0 = q[b];
+                if (r0 < cap) { nt[r0] = c0t; nt[cap + r0] = c0u; nt[2 * cap + r0] = c0v; }
+                const int64_t r1 = r0 + 1;
+                if (adm[b] && r1 < cap) {
+                    nt[r1] = c0t | (axis == 0 ? 1 : 0);
+                    nt[cap + r1] = c0u | (axis == 1 ? 1 : 0);
+                    nt[2 * cap + r1] = c0v | (axis == 2 ? 1 : 0);
+                }
             }
         }
         if (kHead && !tried) {
-            const bool ends = col && (term || cap_level || (!literal && S.tpend <= t0));
+            bool ends = false;
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                ends = ends || (col[b] && (term[b] || cap_level || (!literal && S.tpend <= B.t0[b])));
             if (__ballot(ends) != 0) {
                 tried = true;
-                Acc F = A;
-                wave_reduce_acc(F);
-                acc_uniform(F);
-                const uint64_t g = F.ft;  // packed
-                const int64_t done = b0 + T < cnt ? b0 + T : cnt;
-                // unchecked boxes with keys below g, gathered in LDS
+                KeyAcc F = K;
+                keyacc_reduce(F);
+                const uint64_t g = F.f;
+                const int64_t done = b0 + T < words ? b0 + T : words;
+                // unchecked words holding a key below g, gathered in LDS
                 uint32_t nc = 0;
                 bool fits = true;
-                for (int64_t j0 = done; j0 < cnt; j0 += T) {
+                for (int64_t j0 = done; j0 < words; j0 += T) {
                     const int64_t j = j0 + lane;
-                    const uint64_t k = j < cnt ? ct[j] : ~0ull;
-                    const bool below = j < cnt && k < g;
+                    const uint64_t wd = j < words ? ct[j] : 0;
+                    const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
+                    const bool below = j < words && k0 < g;
                     const uint64_t m = __ballot(below);
                     if (m) {
                         const uint32_t c = (uint32_t)__popcll(m);
                         if (nc + c > 64) { fits = false; break; }
-                        if (below) sh.cand[nc + __popcll(m & lt)] = k;
+                        if (below) sh.cand[nc + __popcll(m & lt)] = wd;
                         nc += c;
                     }
                 }
                 if (fits) {
                     __syncthreads();  // one wavefront: orders the LDS writes before the reads
-                    Acc C;
-                    acc_init(C);
-                    uint64_t ck = ~0ull;
-                    if ((uint32_t)lane < nc) {
-                        ck = sh.cand[lane];
-                        uint64_t xt, xu, xv;
-                        kc.decode(ck, xt, xu, xv);
-                        const double x0 = dyadic(xt, L.bt_bits, L.bt_val);
-                        const double y0 = dyadic(xu, L.bu_bits, L.bu_val);
-                        const double z0 = dyadic(xv, L.bv_bits, L.bv_val);
-                        const CheckResult R = check_box_lds<KIND>(sh.Xs, sh.Es, x0, x0 + L.wt, y0,
-                                                                  y0 + L.wu, z0, z0 + L.wv,
-                                                                  min_sep, delta);
-                        if (R.collide)
-                            acc_add_packed(C, ck, xt, R.small || L.dcap, R.small, false, -1);
+                    const bool cact = (uint32_t)lane < nc;
+                    const uint64_t cw = cact ? sh.cand[lane] : 0;
+                    LaneBoxes C;
+                    expand(cact, cw, 0, 0, C);
+                    check(C);
+                    KeyAcc G;
+                    keyacc_init(G);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        if (C.R[b].collide)
+                            keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small,
+                                       false, -1);
+                    keyacc_reduce(G);
+                    keyacc_merge(F, G);
+                    const uint64_t f = F.f;  // the level's first colliding key
+                    // rank of f: keys below it among checked words and candidates
+                    unsigned long long r = 0;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) r += (C.act[b] && C.key[b] < f) ? 1 : 0;
+                    for (int64_t j = lane; j < done; j += T) {
+                        const uint64_t wd = ct[j];
+                        if (kPair) {
+                            const uint64_t k0 = pair_child(wd, psx, plowx, 0);
+                            r += k0 < f ? 1 : 0;
+                            r += ((wd & kPairFlag) && (k0 | (1ull << psx)) < f) ? 1 : 0;
+                        } else {
+                            r += wd < f ? 1 : 0;
+                        }
                     }
-                    wave_reduce_acc(C);
-                    acc_uniform(C);
-                    acc_merge(F, C);
-                    const uint64_t f = F.ft;  // the level's first colliding key
-                    // rank of f: checked chunks plus gathered candidates
-                    unsigned long long r = ck < f ? 1 : 0;
-                    for (int64_t j = lane; j < done; j += T) r += ct[j] < f ? 1 : 0;
 #pragma unroll
                     for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
                     const uint64_t rf = uni64(r);
-                    uint64_t ft, fu, fv;
-                    kc.decode(f, ft, fu, fv);
-                    F.ft = ft; F.fu = fu; F.fv = fv;
-                    const Outcome O = decide_first(F, S, literal, max_iter, L, rf);
+                    Acc Fa;
+                    acc_init(Fa);
+                    kc.decode(f, Fa.ft, Fa.fu, Fa.fv);
+                    Fa.fflags = F.ff;
+                    const Outcome O = decide_first(Fa, S, literal, max_iter, L, rf);
                     if (O.finish) {
                         early = true;
                         Oe = O;
-                        checked = (uint64_t)done + nc;
+                        checked = boxes_done + (uint64_t)(__popcll(__ballot(C.act[0])) +
+                                                          __popcll(__ballot(C.act[1])));
                         return;
                     }
                 }
             }
         }
     }
-    wave_reduce_acc(A);
-    if (W > 1) {
-        if (lane == 0) sh.acc[wid] = A;
-        __syncthreads();
-        A = sh.acc[0];
-        for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
-        next_cnt = uni64(sh.next_cnt);
-        __syncthreads();
+    checked = S.cnt;
+    if (kPacked) {
+        keyacc_reduce(K);
+        if (W > 1) {
+            if (lane == 0) sh.kacc[wid] = K;
+            __syncthreads();
+            K = sh.kacc[0];
+            for (int w = 1; w < W; ++w) keyacc_merge(K, sh.kacc[w]);
+            next_w = sh.next_cnt;
+            next_b = sh.next_box;
+            __syncthreads();
+            K.f = uni64(K.f); K.m = uni64(K.m); K.tm = uni64(K.tm); K.fpos = uni64s(K.fpos);
+            K.ff = uni32(K.ff); K.mh = uni32(K.mh); K.th = uni32(K.th);
+        }
+        acc_init(A);
+        if (K.ff & 1u) kc.decode(K.f, A.ft, A.fu, A.fv);
+        if (K.mh) kc.decode(K.m, A.mt, A.mu, A.mv);
+        A.fflags = K.ff; A.mhave = K.mh; A.tm = K.tm; A.thave = K.th; A.fpos = K.fpos;
     } else {
-        next_cnt = next_w;
+        wave_reduce_acc(A);
+        if (W > 1) {
+            if (lane == 0) sh.acc[wid] = A;
+            __syncthreads();
+            A = sh.acc[0];
+            for (int w = 1; w < W; ++w) acc_merge(A, sh.acc[w]);
+            next_w = sh.next_cnt;
+            next_b = sh.next_box;
+            __syncthreads();
+        }
+        acc_uniform(A);
     }
-    acc_uniform(A);
-    if (PR) {
-        uint64_t t, u, v;
-        if (A.fflags & 1u) { kc.decode(A.ft, t, u, v); A.ft = t; A.fu = u; A.fv = v; }
-        if (A.mhave) { kc.decode(A.mt, t, u, v); A.mt = t; A.mu = u; A.mv = v; }
-    }
+    next_words = uni64(next_w);
+    next_boxes = uni64(next_b);
 }
 
 // Number of boxes of the level below f and below m (keys as (t, u, v)).
-template <int W, bool PR>
+template <int W, int FIN, int SPLIT>
 __device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct, int64_t cap,
-                                          const State& S, const Acc& A, uint64_t& rf, uint64_t& rm) {
+                                          const State& S, int64_t words, const Acc& A,
+                                          uint64_t& rf, uint64_t& rm) {
     constexpr int T = 64 * W;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -950,9 +1192,18 @@ __device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct
     kc.init(S.d[1], S.d[2]);
     const uint64_t fk = kc.encode(A.ft, A.fu, A.fv);
     const uint64_t mk = kc.encode(A.mt, A.mu, A.mv);
+    const int psx = FIN == kFmtPair ? field_shift(SPLIT, kc) : 0;
+    const uint64_t plowx = mask64(psx);
     unsigned long long sf = 0, sm = 0;
-    for (int64_t i = tid; i < (int64_t)S.cnt; i += T) {
-        if (PR) {
+    for (int64_t i = tid; i < words; i += T) {
+        if (FIN == kFmtPair) {
+            const uint64_t wd = ct[i];
+            const uint64_t k0 = pair_child(wd, psx, plowx, 0);
+            const uint64_t k1 = k0 | (1ull << psx);
+            const bool two = (wd & kPairFlag) != 0;
+            sf += (k0 < fk ? 1 : 0) + ((two && k1 < fk) ? 1 : 0);
+            sm += (k0 < mk ? 1 : 0) + ((two && k1 < mk) ? 1 : 0);
+        } else if (FIN == kFmtKey) {
             const uint64_t k = ct[i];
             sf += k < fk ? 1 : 0;
             sm += k < mk ? 1 : 0;
@@ -980,8 +1231,55 @@ __device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct
 
 __device__ __forceinline__ int depth_sum(const int32_t d[3]) { return d[0] + d[1] + d[2]; }
 
+// Dispatch of one level to the pass for its storage format, pair split axis
+// and output format (all wave-uniform).
+template <int W, int KIND>
+__device__ __forceinline__ void run_level(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
+                                          int64_t cap, const State& S, int64_t words, int fmt,
+                                          int pa, bool op, const LevelInfo& L, double min_sep,
+                                          double delta, bool cap_level, bool literal,
+                                          int64_t max_iter, Acc& A, uint64_t& nw, uint64_t& nb,
+                                          bool& early, Outcome& Oe, uint64_t& checked) {
+#define CCD_PASS(FIN, SP, OPV)                                                                    \
+    level_pass<W, KIND, FIN, SP, OPV>(sh, ct, nt, cap, S, words, L, min_sep, delta, cap_level,    \
+                                      literal, max_iter, A, nw, nb, early, Oe, checked)
+    if (fmt == kFmtPair) {
+        if (op) {
+            if (pa == 0) CCD_PASS(kFmtPair, 0, true);
+            else if (pa == 1) CCD_PASS(kFmtPair, 1, true);
+            else CCD_PASS(kFmtPair, 2, true);
+        } else {
+            if (pa == 0) CCD_PASS(kFmtPair, 0, false);
+            else if (pa == 1) CCD_PASS(kFmtPair, 1, false);
+            else CCD_PASS(kFmtPair, 2, false);
+        }
+    } else if (fmt == kFmtKey) {
+        if (op) CCD_PASS(kFmtKey, 0, true);
+        else CCD_PASS(kFmtKey, 0, false);
+    } else {
+        CCD_PASS(kFmtTriple, 0, false);
+    }
+#undef CCD_PASS
+}
+
+template <int W>
+__device__ __forceinline__ void run_rank(GroupShared<W>& sh, const uint64_t* ct, int64_t cap,
+                                         const State& S, int64_t words, int fmt, int pa,
+                                         const Acc& A, uint64_t& rf, uint64_t& rm) {
+    if (fmt == kFmtPair) {
+        if (pa == 0) rank_pass<W, kFmtPair, 0>(sh, ct, cap, S, words, A, rf, rm);
+        else if (pa == 1) rank_pass<W, kFmtPair, 1>(sh, ct, cap, S, words, A, rf, rm);
+        else rank_pass<W, kFmtPair, 2>(sh, ct, cap, S, words, A, rf, rm);
+    } else if (fmt == kFmtKey) {
+        rank_pass<W, kFmtKey, 0>(sh, ct, cap, S, words, A, rf, rm);
+    } else {
+        rank_pass<W, kFmtTriple, 0>(sh, ct, cap, S, words, A, rf, rm);
+    }
+}
+
 // The level loop of one query, run by the whole block.  The level's boxes are
-// in buffer 0 of the block's arena when it starts.
+// in buffer 0 of the block's arena when it starts, as packed keys when their
+// depth sum allows it, else as triples.
 template <int W, int KIND>
 __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
                                             uint64_t* base, const Record& h, const double kappa[3],
@@ -994,45 +1292,38 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
     S.N = h.N; S.tpend = h.tpend; S.wpend = h.wpend; S.level = h.level;
     S.d[0] = h.d[0]; S.d[1] = h.d[1]; S.d[2] = h.d[2]; S.cnt = h.cnt;
     int cur = 0;
+    int fmt = depth_sum(S.d) <= 64 ? kFmtKey : kFmtTriple;
+    int pa = 0;
+    int64_t words = h.cnt;
     while (true) {
         const LevelInfo L = level_info(kappa, S.d);
         const uint64_t* ct = base + cur * 3 * cap;
         uint64_t* nt = base + (cur ^ 1) * 3 * cap;
-        const bool pr = depth_sum(S.d) <= 64;
-        const bool pw = depth_sum(S.d) + 1 <= 64;
+        // pairs need this level's keys packed with a spare top bit
+        const bool op = fmt != kFmtTriple && depth_sum(S.d) <= 63;
         const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
         Acc A;
-        uint64_t next_cnt = 0, checked = 0;
+        uint64_t nw = 0, nb = 0, checked = 0;
         bool early;
         Outcome Oe;
-        if (pw)
-            level_pass<W, KIND, true, true>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, literal,
-                                            max_iter, A, next_cnt, early, Oe, checked);
-        else if (pr)
-            level_pass<W, KIND, true, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level, literal,
-                                             max_iter, A, next_cnt, early, Oe, checked);
-        else
-            level_pass<W, KIND, false, false>(sh, ct, nt, cap, S, L, min_sep, delta, cap_level,
-                                              literal, max_iter, A, next_cnt, early, Oe, checked);
+        run_level<W, KIND>(sh, ct, nt, cap, S, words, fmt, pa, op, L, min_sep, delta, cap_level,
+                           literal, max_iter, A, nw, nb, early, Oe, checked);
         if (tid == 0) {
             nchk += checked;
-            slots += (uint64_t)((checked + T - 1) / T) * T;
+            slots += (uint64_t)((words + T - 1) / T) * T * (fmt == kFmtPair ? 2 : 1);
         }
         if (early) {
             if (tid == 0) write_result(a, h.q, Oe);
             return;
         }
         uint64_t rf = 0, rm = 0;
-        if (need_rank(A, S, literal, max_iter, L)) {
-            if (pr) rank_pass<W, true>(sh, ct, cap, S, A, rf, rm);
-            else rank_pass<W, false>(sh, ct, cap, S, A, rf, rm);
-        }
+        if (need_rank(A, S, literal, max_iter, L)) run_rank<W>(sh, ct, cap, S, words, fmt, pa, A, rf, rm);
         const Outcome O = decide(A, S, literal, max_iter, L, rf, rm);
         if (O.finish) {
             if (tid == 0) write_result(a, h.q, O);
             return;
         }
-        if (next_cnt > (uint64_t)cap) {
+        if (nw > (uint64_t)cap) {
             // the next level does not fit: restart the query in the next engine
             if (tid == 0) {
                 bool placed = false;
@@ -1055,22 +1346,26 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
             }
             return;
         }
-        // f is colliding and not terminal here, so its child 0 is on the next
-        // level, where it is the smallest key (Alg. 2 order is preserved by
-        // bisection): store it first, where the head try looks first
+        // f is colliding and not terminal here, so its word (pairs) or child 0
+        // (triples) is on the next level and holds that level's smallest key
+        // (bisection preserves Alg. 2's order): store it first, where the head
+        // try looks first
         if (A.fpos > 0) {
             __syncthreads();
             if (tid == 0) {
                 const int64_t p = A.fpos;
-                const int words = pw ? 1 : 3;
-                for (int w = 0; w < words; ++w) {
+                const int nwords = op ? 1 : 3;
+                for (int w = 0; w < nwords; ++w) {
                     const uint64_t x0 = nt[w * cap], xp = nt[w * cap + p];
                     nt[w * cap] = xp;
                     nt[w * cap + p] = x0;
                 }
             }
         }
-        advance(S, A, literal, L, (uint32_t)next_cnt);
+        advance(S, A, literal, L, (uint32_t)nb);
+        fmt = op ? kFmtPair : kFmtTriple;
+        pa = L.axis;
+        words = (int64_t)nw;
         cur ^= 1;
         __syncthreads();
     }
