@@ -2,7 +2,7 @@
 
 One step = one ccd_batch call over the whole workload (all queries resident in
 HBM before the timed region), i.e. the complete root finder for every query:
-kind partition, lane engine, group engine and block engine.  Default
+root pass (level 0 of every query), lane engine, group engine and block engine.  Default
 workload: 1,000,000 simulation-shaped queries (60% vertex-face, 40%
 edge-edge, 2% near-contacts, 1% grazing contacts), delta = 1e-6, m_I = 1e6,
 no minimum separation.  Prints one JSON line.
@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "CCD queries/s at delta=1e-6 (persistent vs plain kernel); p50/p99 serve latency"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk (FMA = 2)
 FLOP_PER_CHECK = {0: 227.0, 1: 177.0}  # vertex-face, edge-edge box check (binary64 add/sub/mul)
-KERNELS = ("partition", "lane", "group", "block")
+KERNELS = ("root", "lane", "group", "block")
 
 
 def make_workload(name: str, n: int | None):

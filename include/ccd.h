@@ -221,11 +221,12 @@ int ccd_context_graph_counts(ccd_context* ctx, uint64_t* builds, uint64_t* repla
 
 /* Counters of the last ccd_batch on a context (host copy; synchronises). */
 typedef struct ccd_stats {
-    uint64_t checks[3][2];   /* box checks executed by tier [lane, group, block] x kind [VF, EE] */
+    uint64_t checks[3][2];   /* box checks executed by tier [lane, group, block] x kind [VF, EE];
+                                the lane tier includes the root pass */
     uint64_t promoted[2];    /* queries handed to the group tier, to the block tier */
     uint64_t lane_slots[3];  /* lane-iterations spent per tier; checks / lane_slots is the
                                 fraction of SIMD lanes doing box checks */
-    float kernel_ms[4];      /* device time of [partition, lane, group, block] kernels
+    float kernel_ms[4];      /* device time of [root pass, lane, group, block] kernels
                                 (only when timing is enabled, else 0) */
 } ccd_stats;
 int ccd_context_enable_timing(ccd_context* ctx, int enable);

@@ -7,8 +7,8 @@ namespace ccd {
 // Device counters (uint64 each) kept in one small scratch array per context.
 enum Counter : int {
     kCntCursor = 0,      // lane engine: next index into the query order
-    kCntOrderFront,      // partition: next VF slot
-    kCntOrderBack,       // partition: next EE slot (counts down from n)
+    kCntOrderFront,      // root pass: next VF slot
+    kCntOrderBack,       // root pass: next EE slot (counts down from n)
     kCntRecA,            // records handed from the lane engine to the group engine
     kCntRecATake,        // group engine: next record to take
     kCntRecB,            // records handed from the group engine to the block engine
@@ -82,6 +82,8 @@ constexpr int kRecordHeaderWords = 8;  // header padded to 64 bytes
 struct LaneCfg {
     int32_t capacity;          // boxes per level per lane
     int32_t persistent;        // 1: lanes pull queries from the cursor
+    int32_t survivors;         // 1: the queries are the root pass's list in order
+    int32_t pad;
     uint64_t budget;           // checks after which a query is handed on
     uint64_t* arena;           // lane frontiers: [slots][2][capacity][3][64]
     uint64_t* records;         // promotion records, stride record_words

@@ -429,26 +429,81 @@ __device__ __forceinline__ void acc_uniform(Acc& A) {
 }
 
 // ---------------------------------------------------------------------------
-// Query order grouped by kind (VF from the front, EE from the back), so that
-// the lanes of a wavefront mostly run the same corner formula.
-
-__global__ void k_partition(BatchArgs a, int64_t* order) {
+// Level 0 of every query, one thread per query (Alg. 2's first pop: the box
+// [0,1]^3).  Invalid queries get their invalid result.  A query whose root box
+// does not collide is finished after one check; so is one whose root box is
+// terminal or whose m_I is 1 (n = 1, toi = 0).  The others are listed in
+// `order` for the lane engine, vertex-face ones from the front and edge-edge
+// ones from the back (counts in kCntOrderFront / kCntOrderBack), so that its
+// wavefronts mostly run one corner formula; the lane engine checks their root
+// box again (it needs the level-0 corners for kappa) and counts that check.
+__global__ __launch_bounds__(1024) void k_root(BatchArgs a, int64_t* order) {
+    __shared__ unsigned int cnt[2];
+    __shared__ unsigned long long base[2];
+    __shared__ unsigned int fin[2];
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool act = q < a.n;
-    const int kind = act ? query_kind(a, q) : 0;
-    const bool ee = act && kind == kEE;
-    const bool vf = act && !ee;
-    const uint64_t mv = __ballot(vf), me = __ballot(ee);
     const int lane = __lane_id();
-    unsigned long long bv = 0, be = 0;
-    if (lane == 0) {
-        if (mv) bv = atomicAdd(&a.counters[kCntOrderFront], (unsigned long long)__popcll(mv));
-        if (me) be = atomicAdd(&a.counters[kCntOrderBack], (unsigned long long)__popcll(me));
+    if (threadIdx.x < 2) { cnt[threadIdx.x] = 0; fin[threadIdx.x] = 0; }
+    __syncthreads();
+    bool keep = false, done = false;
+    int kind = 0;
+    if (q < a.n) {
+        Query Q;
+        bool valid;
+        load_query(a, q, Q, valid);
+        kind = Q.kind;
+        if (!valid) {
+            write_invalid(a, q);
+        } else {
+            double kap[3];
+            const CheckResult R = Q.kind == kEE
+                ? box_check<kEE>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap)
+                : box_check<kVF>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap);
+            // Alg. 2's decision on a one-box level 0
+            State S;
+            S.N = 0; S.tpend = INFINITY; S.wpend = 0.0; S.level = 0;
+            S.d[0] = S.d[1] = S.d[2] = 0; S.cnt = 1;
+            LevelInfo L;
+            L.wt = L.wu = L.wv = 1.0;
+            Acc A;
+            acc_init(A);
+            if (R.collide) acc_add(A, 0, 0, 0, R.small, R.small);
+            const Outcome O = decide(A, S, Q.literal, Q.max_iter, L, 0, 0);
+            if (O.finish) {
+                write_result(a, q, O);
+                done = true;
+            } else {
+                keep = true;
+            }
+        }
     }
-    bv = __shfl(bv, 0);
-    be = __shfl(be, 0);
-    if (vf) order[bv + __popcll(mv & lanemask_lt())] = q;
-    if (ee) order[a.n - 1 - (int64_t)(be + __popcll(me & lanemask_lt()))] = q;
+    const bool ee = keep && kind == kEE;
+    const bool vf = keep && !ee;
+    const uint64_t mv = __ballot(vf), me = __ballot(ee);
+    const uint64_t dv = __ballot(done && kind != kEE), de = __ballot(done && kind == kEE);
+    unsigned int ov = 0, oe = 0;
+    if (lane == 0) {
+        if (mv) ov = atomicAdd(&cnt[0], (unsigned int)__popcll(mv));
+        if (me) oe = atomicAdd(&cnt[1], (unsigned int)__popcll(me));
+        if (dv) atomicAdd(&fin[0], (unsigned int)__popcll(dv));
+        if (de) atomicAdd(&fin[1], (unsigned int)__popcll(de));
+    }
+    ov = __shfl(ov, 0);
+    oe = __shfl(oe, 0);
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        if (cnt[threadIdx.x])
+            base[threadIdx.x] = atomicAdd(&a.counters[threadIdx.x == 0 ? kCntOrderFront : kCntOrderBack],
+                                          (unsigned long long)cnt[threadIdx.x]);
+        // one check per query finished here; the survivors' root checks are
+        // counted once, by the lane engine
+        if (fin[threadIdx.x])
+            atomicAdd(&a.counters[kCntChecks + threadIdx.x], (unsigned long long)fin[threadIdx.x]);
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    if (vf) order[base[0] + ov + __popcll(mv & lt)] = q;
+    if (ee) order[a.n - 1 - (int64_t)(base[1] + oe + __popcll(me & lt))] = q;
 }
 
 // Resets the counters at the start of a batch (a kernel, so that it can sit
@@ -492,6 +547,14 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
     int cur = 0;
     uint64_t nchk[2] = {0, 0};
     uint64_t iters = 0;
+    // persistent: the queries are the root pass's survivors, vertex-face at
+    // order[0, nf) and edge-edge at order[n - ne, n), taken as one range
+    uint64_t total = (uint64_t)a.n, nf = 0, ne = 0;
+    if (PERSISTENT && c.survivors) {
+        nf = uni64(a.counters[kCntOrderFront]);
+        ne = uni64(a.counters[kCntOrderBack]);
+        total = nf + ne;
+    }
 
     while (true) {
         if (PERSISTENT && !exhausted) {
@@ -505,12 +568,13 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 base = uni64(__shfl(base, leader));
                 if (need) {
                     const uint64_t r = base + __popcll(m & lanemask_lt());
-                    if (r < (uint64_t)a.n) {
-                        q = a.order ? a.order[r] : (int64_t)r;
+                    if (r < total) {
+                        const uint64_t o = (c.survivors && r >= nf) ? (uint64_t)a.n - ne + (r - nf) : r;
+                        q = a.order ? a.order[o] : (int64_t)o;
                         fresh = true;
                     }
                 }
-                if (base + __popcll(m) >= (uint64_t)a.n) exhausted = true;
+                if (base + __popcll(m) >= total) exhausted = true;
             }
         }
         if (__ballot(q >= 0) == 0) break;

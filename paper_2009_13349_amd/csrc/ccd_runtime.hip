@@ -1,7 +1,8 @@
 // Host runtime and C ABI of the MI355X CCD library (see include/ccd.h).
 //
 // A batch runs as a fixed sequence of kernels on the caller's stream:
-//   reset counters -> [partition queries by kind] -> lane engine ->
+//   reset counters -> [root pass: level 0 of every query, survivors grouped
+//   by kind] -> lane engine ->
 //   group engine (wide queries handed on by the lane engine) ->
 //   block engine (queries whose frontier outgrew a group arena).
 // All scratch lives in one context, sized within the context's memory budget
@@ -27,7 +28,7 @@ template <bool P>
 __global__ void k_lane(BatchArgs a, LaneCfg c);
 template <int W, int OCC>
 __global__ void k_group(BatchArgs a, GroupCfg g);
-__global__ void k_partition(BatchArgs a, int64_t* order);
+__global__ void k_root(BatchArgs a, int64_t* order);
 __global__ void k_reset(unsigned long long* counters);
 }  // namespace ccd
 
@@ -218,8 +219,9 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
     a.order = nullptr;
     if (timed) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
-    if (persistent && (a.kind || a.reqs)) {
-        hipLaunchKernelGGL(k_partition, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, a,
+    if (persistent) {
+        // level 0 of every query; the survivors, grouped by kind, go on
+        hipLaunchKernelGGL(k_root, dim3((unsigned)((P.n + 1023) / 1024)), dim3(1024), 0, s, a,
                            (int64_t*)ctx->order.p);
         a.order = (const int64_t*)ctx->order.p;
     }
@@ -227,6 +229,8 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
     LaneCfg lc;
     lc.capacity = K;
     lc.persistent = persistent ? 1 : 0;
+    lc.survivors = persistent ? 1 : 0;
+    lc.pad = 0;
     lc.budget = persistent ? (uint64_t)ctx->tune.lane_budget : ~0ull;
     lc.arena = (uint64_t*)ctx->lane_arena.p;
     lc.records = (uint64_t*)ctx->rec_a.p;
