@@ -1360,7 +1360,11 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
     int pa = 0;
     int64_t words = h.cnt;
     while (true) {
-        const LevelInfo L = level_info(kappa, S.d);
+        LevelInfo L = level_info(kappa, S.d);
+        // equal in every lane: keep the level's description in scalar registers
+        L.axis = (int)uni32((uint32_t)L.axis);
+        L.dcap = uni32(L.dcap ? 1u : 0u) != 0;
+        L.wt = unif64(L.wt); L.wu = unif64(L.wu); L.wv = unif64(L.wv);
         const uint64_t* ct = base + cur * 3 * cap;
         uint64_t* nt = base + (cur ^ 1) * 3 * cap;
         // pairs need this level's keys packed with a spare top bit
