@@ -408,6 +408,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Set bits of two wavefront masks in the lanes below this one (mbcnt).
+__device__ __forceinline__ int below_lane(uint64_t m0, uint64_t m1) {
+    unsigned int c = __builtin_amdgcn_mbcnt_lo((unsigned int)m0, 0u);
+    c = __builtin_amdgcn_mbcnt_hi((unsigned int)(m0 >> 32), c);
+    c = __builtin_amdgcn_mbcnt_lo((unsigned int)m1, c);
+    c = __builtin_amdgcn_mbcnt_hi((unsigned int)(m1 >> 32), c);
+    return (int)c;
+}
+
 // Values that are equal in every lane (LDS broadcasts, butterfly reductions)
 // made provably wave-uniform, so that they live in scalar registers and the
 // branches on them are scalar branches.
@@ -1095,22 +1104,44 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         }
         if (OP) {
             // one word per stored box; mk[2], mk[3] only count boxes
-            q[0] = (int64_t)wbase + __popcll(mk[0] & lt) + __popcll(mk[1] & lt);
+            q[0] = (int64_t)wbase + below_lane(mk[0], mk[1]);
             q[1] = q[0] + (e[0] ? 1 : 0);
         } else {
             // up to four child triples per lane, all counted by mk[0..3]
-            int64_t o = (int64_t)wbase;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) o += __popcll(mk[j] & lt);
-            q[0] = o;
-            q[1] = o + (e[0] ? 1 : 0) + (e[0] && adm[0] ? 1 : 0);
+            q[0] = (int64_t)wbase + below_lane(mk[0], mk[1]) + below_lane(mk[2], mk[3]);
+            q[1] = q[0] + (e[0] ? 1 : 0) + (e[0] && adm[0] ? 1 : 0);
         }
+        if (kPacked) {
+            // smallest colliding key, every level
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            if (!col[b]) continue;
-            const int64_t pos = (e[b] && q[b] < cap) ? q[b] : -1;
-            if (kPacked) keyacc_add(K, B.key[b], B.it[b], term[b], B.R[b].small, cap_level, pos);
-            else acc_add(A, B.it[b], B.iu[b], B.iv[b], term[b], B.R[b].small, cap_level, pos);
+            for (int b = 0; b < 2; ++b) {
+                const int64_t pos = (e[b] && q[b] < cap) ? q[b] : -1;
+                const uint32_t fl = 1u | (term[b] ? 2u : 0u) | (B.R[b].small ? 4u : 0u);
+                if (col[b] && (!(K.ff & 1u) || B.key[b] < K.f)) {
+                    K.f = B.key[b];
+                    K.ff = fl;
+                    K.fpos = pos;
+                }
+            }
+            // largest colliding key: only on a level where m_I can stop
+            if (cap_level) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (col[b] && (!K.mh || K.m < B.key[b])) { K.m = B.key[b]; K.mh = 1; }
+            }
+            // terminal colliding boxes (the carried box): rare before the last level
+            if (__ballot((col[0] && term[0]) || (col[1] && term[1])) != 0) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (col[b] && term[b] && (!K.th || B.it[b] < K.tm)) { K.tm = B.it[b]; K.th = 1; }
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (!col[b]) continue;
+                const int64_t pos = (e[b] && q[b] < cap) ? q[b] : -1;
+                acc_add(A, B.it[b], B.iu[b], B.iv[b], term[b], B.R[b].small, cap_level, pos);
+            }
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
