@@ -81,10 +81,14 @@ def lib():
         L.oracle_solve.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int64,
                                    ctypes.c_double, ctypes.c_int, ctypes.POINTER(OracleResult)]
         L.oracle_solve.restype = ctypes.c_int
+        L.oracle_solve_tmax.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int64,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(OracleResult)]
+        L.oracle_solve_tmax.restype = ctypes.c_int
         L.oracle_solve_batch.argtypes = [
             ctypes.c_int64, _D, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
             _D, ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
-            _D, ctypes.c_double, ctypes.c_int,
+            _D, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             _D, _D, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint64),
             ctypes.POINTER(ctypes.c_uint8)]
         L.oracle_solve_batch.restype = ctypes.c_int64
@@ -148,19 +152,20 @@ def validate(X, delta: float, max_iter: int, min_sep: float = 0.0) -> bool:
 
 
 def solve(kind: int, X, delta: float = 1e-6, max_iter: int = 1_000_000, min_sep: float = 0.0,
-          literal: bool = False) -> OracleResult:
-    """Algorithm 2 on one query; raises ValueError on invalid input."""
+          literal: bool = False, t_max: float = 1.0) -> OracleResult:
+    """Algorithm 2 on one query over I = [0, t_max] x [0,1]^2; raises ValueError on
+    invalid input.  The result's box keeps the time axis normalized (t / t_max)."""
     X = _as_x(X)
     r = OracleResult()
-    rc = lib().oracle_solve(kind, _dptr(X), delta, int(max_iter), min_sep, int(literal),
-                            ctypes.byref(r))
+    rc = lib().oracle_solve_tmax(kind, _dptr(X), delta, int(max_iter), min_sep, float(t_max),
+                                 int(literal), ctypes.byref(r))
     if rc != 0:
         raise ValueError("invalid CCD query")
     return r
 
 
 def solve_batch(pos: np.ndarray, kind=None, default_kind: int = 0, delta=1e-6,
-                max_iter=1_000_000, min_sep=0.0, literal: bool = False):
+                max_iter=1_000_000, min_sep=0.0, literal: bool = False, t_max: float = 1.0):
     """Batch over SoA positions pos[24, n]. delta/max_iter/min_sep may be scalars
     or per-query arrays. Returns a dict of numpy arrays."""
     pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
@@ -186,7 +191,7 @@ def solve_batch(pos: np.ndarray, kind=None, default_kind: int = 0, delta=1e-6,
         n, _dptr(pos), None if kind_a is None else kind_a.ctypes.data_as(u8), default_kind,
         None if dq is None else _dptr(dq), float(ds),
         None if mq is None else mq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(ms_),
-        None if sq is None else _dptr(sq), float(ss), int(literal),
+        None if sq is None else _dptr(sq), float(ss), float(t_max), int(literal),
         _dptr(toi), _dptr(tw), hit.ctypes.data_as(u8),
         nc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), st.ctypes.data_as(u8))
     return {"toi": toi, "t_width": tw, "hit": hit, "n_checks": nc, "status": st,

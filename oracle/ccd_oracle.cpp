@@ -35,6 +35,11 @@
 //     is already at depth 52 is treated as terminal, so every endpoint and every
 //     complement 1-t, 1-u, (1-u)-v stays exact.
 //   * n_checks is reported saturated at m_I.
+//   * shortened time interval (Sec. 6, line search: only the initial I changes):
+//     I_t = [0, t_max], 0 < t_max <= 1, bisected in the normalized coordinate
+//     s = t / t_max; a box's time endpoints are fl(t_max * s) and its width is
+//     w(I_t) = t_max * w(I_s) (exact).  kappa keeps eq. kappas (corners at
+//     t = 0 and t = 1: a per-unit slope).  ORDER compares s, which orders like t.
 #include <cmath>
 #include <cstdint>
 #include <queue>
@@ -52,7 +57,8 @@ struct oracle_result {
     uint8_t hit;         // toi <= 1
     uint8_t status;      // ORACLE_ST_* bits
     uint8_t pad[6];
-    double box[6];       // t_lo, t_hi, u_lo, u_hi, v_lo, v_hi of the returned box
+    double box[6];       // t_lo, t_hi, u_lo, u_hi, v_lo, v_hi of the returned box (time
+                         // endpoints normalized: t / t_max)
     int32_t level;
     int32_t depth[3];
 };
@@ -259,10 +265,13 @@ static void fill_result(oracle_result* out, double toi, double tw, uint64_t n, i
     }
 }
 
-int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, double min_sep,
-                 int literal, oracle_result* out) {
+// Alg. 2 on I = [0, t_max] x [0,1]^2.  Box.t holds the normalized time
+// interval (s); time values are fl(t_max * s).
+int oracle_solve_tmax(int kind, const double X[24], double delta, int64_t max_iter,
+                      double min_sep, double t_max, int literal, oracle_result* out) {
     if (kind != ORACLE_VF && kind != ORACLE_EE) return ORACLE_EINVAL;
     if (oracle_validate(X, delta, max_iter, min_sep) != ORACLE_OK) return ORACLE_EINVAL;
+    if (!(t_max > 0.0 && t_max <= 1.0)) return ORACLE_EINVAL;
 
     double eps[3], kappa[3];
     oracle_filter(kind, X, min_sep, eps);
@@ -281,7 +290,8 @@ int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, d
     while (!Q.empty()) {
         Box I = Q.top();
         Q.pop();
-        double box[6] = {I.t[0], I.t[1], I.u[0], I.u[1], I.v[0], I.v[1]};
+        const double t_lo = t_max * I.t[0];
+        double box[6] = {t_lo, t_max * I.t[1], I.u[0], I.u[1], I.v[0], I.v[1]};
         int collide, inside;
         double width;
         oracle_box_check(kind, X, box, eps, min_sep, &collide, &inside, &width, nullptr, nullptr);
@@ -289,31 +299,31 @@ int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, d
         if (!collide) continue;
 
         bool first = (I.level != lp);
-        double w_t = I.t[1] - I.t[0];
+        double w_t = t_max * (I.t[1] - I.t[0]);
         if (first) {
             If = I;
-            if (!literal && t_pend <= I.t[0]) {
+            if (!literal && t_pend <= t_lo) {
                 fill_result(out, t_pend, w_pend, n, max_iter, ORACLE_ST_CARRY, &pend_box);
                 return ORACLE_OK;
             }
         }
         if (n >= (uint64_t)max_iter) {
-            fill_result(out, If.t[0], w_t, n, max_iter, ORACLE_ST_CAP, &If);
+            fill_result(out, t_max * If.t[0], w_t, n, max_iter, ORACLE_ST_CAP, &If);
             return ORACLE_OK;
         }
 
-        double widths[3] = {I.t[1] - I.t[0], I.u[1] - I.u[0], I.v[1] - I.v[0]};
+        double widths[3] = {w_t, I.u[1] - I.u[0], I.v[1] - I.v[0]};
         int axis = oracle_split_axis(kappa, widths);
         bool depth_capped = I.depth[axis] >= kMaxDepth;
         bool small = (width < delta) || inside;
         if (small || depth_capped) {
             if (first) {
                 uint8_t st = small ? 0 : ORACLE_ST_DEPTH;
-                fill_result(out, I.t[0], w_t, n, max_iter, st, &I);
+                fill_result(out, t_lo, w_t, n, max_iter, st, &I);
                 return ORACLE_OK;
             }
-            if (!literal && I.t[0] < t_pend) {
-                t_pend = I.t[0];
+            if (!literal && t_lo < t_pend) {
+                t_pend = t_lo;
                 w_pend = w_t;
                 pend_box = I;
             }
@@ -343,14 +353,19 @@ int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, d
     return ORACLE_OK;
 }
 
+int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, double min_sep,
+                 int literal, oracle_result* out) {
+    return oracle_solve_tmax(kind, X, delta, max_iter, min_sep, 1.0, literal, out);
+}
+
 // Batch driver over the structure-of-arrays layout pos[(3k+c)*n + q]. Per-query
 // parameters are optional (NULL selects the scalar value). Returns the number of
 // invalid queries (their status is 0xFF, toi NaN).
 int64_t oracle_solve_batch(int64_t n, const double* pos, const uint8_t* kind, int default_kind,
                            const double* delta_q, double delta, const int64_t* max_iter_q,
-                           int64_t max_iter, const double* min_sep_q, double min_sep, int literal,
-                           double* toi, double* t_width, uint8_t* hit, uint64_t* n_checks,
-                           uint8_t* status) {
+                           int64_t max_iter, const double* min_sep_q, double min_sep, double t_max,
+                           int literal, double* toi, double* t_width, uint8_t* hit,
+                           uint64_t* n_checks, uint8_t* status) {
     int64_t bad = 0;
     for (int64_t q = 0; q < n; ++q) {
         double X[24];
@@ -360,7 +375,7 @@ int64_t oracle_solve_batch(int64_t n, const double* pos, const uint8_t* kind, in
         int64_t mi = max_iter_q ? max_iter_q[q] : max_iter;
         double ms = min_sep_q ? min_sep_q[q] : min_sep;
         oracle_result r;
-        if (oracle_solve(k, X, dl, mi, ms, literal, &r) != ORACLE_OK) {
+        if (oracle_solve_tmax(k, X, dl, mi, ms, t_max, literal, &r) != ORACLE_OK) {
             ++bad;
             toi[q] = NAN; t_width[q] = NAN; hit[q] = 0; n_checks[q] = 0; status[q] = 0xFF;
             continue;
