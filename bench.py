@@ -37,12 +37,12 @@ def make_workload(name: str, n: int | None):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup, timing=True):
+def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup, timing=True, t_max=1.0):
     from paper_2009_13349_amd import ccd
     ctx.set_engine(engine)
     ctx.enable_timing(timing)
     out = None
-    kw = dict(delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    kw = dict(delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"], t_max=t_max)
     for _ in range(warmup):
         out = ctx.batch_device(pos, kind, out=out, **kw)
         ctx.last_stats()
@@ -267,6 +267,21 @@ def main():
         plain = {"value": round(n * args.steps / t_b, 1), "ms_per_step": round(1e3 * t_b / args.steps, 3),
                  "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
                                    for i in range(4)}}
+    # the line search's shortened interval (Sec. 6): same queries over t in
+    # [0, 0.5], then the batch-wide smallest toi (the step bound)
+    t_s, _, out_s = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps, 1,
+                               timing=False, t_max=0.5)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mt = ctx.min_toi(out_s.toi)
+    ev0.record()
+    for _ in range(10):
+        mt = ctx.min_toi(out_s.toi, out=mt)
+    ev1.record()
+    torch.cuda.synchronize()
+    shortened = {"t_max": 0.5, "value": round(n * args.steps / t_s, 1),
+                 "ms_per_step": round(1e3 * t_s / args.steps, 3),
+                 "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
+                 "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
     rl = roofline(stats_p, kind_counts)
     tier = KERNELS.index(rl["kernel"]) - 1
     rl["symbol"] = kernel_symbol(tier, ctx.tuning())
@@ -309,6 +324,7 @@ def main():
         "lane_utilization": [round(sum(stats_p[-1]["checks"][i]) / stats_p[-1]["lane_slots"][i], 3)
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,
+        "shortened_interval": shortened,
     }
     line["serve"] = (serve_latency(w, torch, value, args.serve_requests)
                      if args.serve_requests > 0 and args.workload == "simulation" else None)

@@ -30,10 +30,17 @@
  *   - A query is invalid if a coordinate is not finite or exceeds 1e300 in
  *     magnitude, delta is not a positive finite number, max_iter < 1, min_sep is
  *     negative or not finite, min_sep is not below min_c gamma_c (Sec. 5.1
- *     assumes d < gamma), or t_max != 1.
+ *     assumes d < gamma).  A batch is rejected (CCD_EINVAL) when t_max is not
+ *     in (0, 1].
  *   - Output convention (Alg. 2): hit = (toi <= 1); no collision is
  *     toi = +inf, t_width = 0.  toi is a conservative (never late) estimate of
  *     the earliest contact time; t_width is w(I_t) of the level it came from.
+ *   - Shortened time interval (Sec. 6, line search: only the initial interval
+ *     of Alg. 2 changes): with t_max < 1 the search covers t in [0, t_max].  The
+ *     time axis is bisected in s = t / t_max and a box's time endpoints are
+ *     fl(t_max * s); toi is such an endpoint and t_width = t_max * 2^-depth.
+ *     kappa_t keeps eq. kappas (F at t = 0 and t = 1), and the split rule uses
+ *     w(I_t) = t_max * 2^-depth.  t_max = 1 is the standard query.
  */
 #ifndef CCD_H
 #define CCD_H
@@ -79,7 +86,7 @@ typedef struct ccd_params {
     double delta;      /* tolerance delta > 0 on the co-domain width; paper default 1e-6 */
     int64_t max_iter;  /* m_I >= 1: maximum number of box checks; paper default 1e6 */
     double min_sep;    /* d >= 0: minimum separation, L-infinity; 0 = standard CCD */
-    double t_max;      /* must be 1.0 (reserved for a shortened time interval) */
+    double t_max;      /* 0 < t_max <= 1: search t in [0, t_max]; paper default 1 */
     uint32_t flags;    /* CCD_FLAG_* */
     uint32_t reserved; /* must be 0 */
 } ccd_params;
@@ -231,6 +238,18 @@ typedef struct ccd_stats {
 } ccd_stats;
 int ccd_context_enable_timing(ccd_context* ctx, int enable);
 int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
+
+/*
+ * Smallest toi of a batch, for a line search: the step length is bounded by
+ * the earliest time of impact over the candidate pairs (Sec. 6, Alg. 4: alpha
+ * = min(t, alpha) over the MSCCD calls).  toi: n device doubles (a result's
+ * toi array); out: one device double, 8-byte aligned.  Asynchronous on
+ * `stream` (0 = default), ordered after the batch that wrote toi when issued
+ * on the same stream.  NaN entries (invalid queries) are skipped; *out = +inf
+ * when n = 0 or no entry is finite.  Returns CCD_EINVAL for a null pointer
+ * with n > 0, n < 0 or a misaligned out, CCD_EDEVICE on a HIP error.
+ */
+int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /*

@@ -27,7 +27,7 @@ EXPORTED = [
     "ccd_context_set_engine", "ccd_context_get_tuning", "ccd_context_set_tuning", "ccd_batch",
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
     "ccd_context_enable_graphs", "ccd_context_graph_counts", "ccd_autotune",
-    "ccd_tuning_cache_store", "ccd_tuning_cache_load",
+    "ccd_tuning_cache_store", "ccd_tuning_cache_load", "ccd_min_toi",
 ]
 
 
@@ -116,6 +116,7 @@ def _lib():
         L.ccd_tuning_cache_load.argtypes = [V, ctypes.c_char_p, ctypes.c_char_p]
         L.ccd_context_graph_counts.argtypes = [V, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.ccd_context_last_stats.argtypes = [V, P(Stats)]
+        L.ccd_min_toi.argtypes = [V, V, ctypes.c_int64, V, V]
         L.ccd_strerror.argtypes = [ctypes.c_int]
         L.ccd_strerror.restype = ctypes.c_char_p
         L.ccd_last_error.argtypes = []
@@ -129,19 +130,20 @@ def load():
     return _lib()
 
 
-def params(delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Params:
+def params(delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False, t_max=1.0) -> Params:
     p = Params()
     _lib().ccd_params_default(ctypes.byref(p))
     p.delta, p.max_iter, p.min_sep = float(delta), int(max_iter), float(min_sep)
+    p.t_max = float(t_max)
     p.flags = FLAG_LITERAL if literal else 0
     return p
 
 
-def _single(fn, X, delta, max_iter, min_sep, literal):
+def _single(fn, X, delta, max_iter, min_sep, literal, t_max):
     X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(8, 3))
     a = ((ctypes.c_double * 3) * 4)(*[(ctypes.c_double * 3)(*X[k]) for k in range(4)])
     b = ((ctypes.c_double * 3) * 4)(*[(ctypes.c_double * 3)(*X[k]) for k in range(4, 8)])
-    p = params(delta, max_iter, min_sep, literal)
+    p = params(delta, max_iter, min_sep, literal, t_max)
     r = Result()
     D43 = ctypes.POINTER(ctypes.c_double * 3)
     rc = fn(ctypes.cast(a, D43), ctypes.cast(b, D43), ctypes.byref(p), ctypes.byref(r))
@@ -150,14 +152,14 @@ def _single(fn, X, delta, max_iter, min_sep, literal):
     return r
 
 
-def vf(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Result:
+def vf(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False, t_max=1.0) -> Result:
     """One vertex-face query (24 doubles: p, v1, v2, v3 at t0 then at t1) on the GPU."""
-    return _single(_lib().ccd_vf, X, delta, max_iter, min_sep, literal)
+    return _single(_lib().ccd_vf, X, delta, max_iter, min_sep, literal, t_max)
 
 
-def ee(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False) -> Result:
+def ee(X, delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False, t_max=1.0) -> Result:
     """One edge-edge query (24 doubles: p1, p2, p3, p4 at t0 then at t1) on the GPU."""
-    return _single(_lib().ccd_ee, X, delta, max_iter, min_sep, literal)
+    return _single(_lib().ccd_ee, X, delta, max_iter, min_sep, literal, t_max)
 
 
 @dataclass
@@ -265,7 +267,7 @@ class Context:
 
     def _device_desc(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
                      min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
-                     out: BatchResult | None = None, stream=None):
+                     out: BatchResult | None = None, stream=None, t_max=1.0):
         import torch
         assert pos.is_cuda and pos.dtype == torch.float64 and pos.dim() == 2 and pos.shape[0] == 24
         pos = pos.contiguous()
@@ -295,7 +297,7 @@ class Context:
                 assert arr.dtype == dt and arr.is_cuda and arr.numel() == n
                 keep.append(arr)
                 setattr(d, name, arr.data_ptr())
-        d.params = params(delta, max_iter, min_sep, literal)
+        d.params = params(delta, max_iter, min_sep, literal, t_max)
         d.on_device = 1
         o = ResultSoA(out.toi.data_ptr(), out.t_width.data_ptr(), out.hit.data_ptr(),
                       out.n_checks.data_ptr(), out.status.data_ptr())
@@ -305,12 +307,12 @@ class Context:
 
     def batch_device(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
                      min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
-                     out: BatchResult | None = None, stream=None) -> BatchResult:
+                     out: BatchResult | None = None, stream=None, t_max=1.0) -> BatchResult:
         """Asynchronous batch on device tensors (torch): pos float64 [24, n],
         kind uint8 [n].  Results are torch tensors on the same device."""
         d, o, out, keep, stream = self._device_desc(
             pos, kind, default_kind, delta, max_iter, min_sep, literal, delta_q, max_iter_q,
-            min_sep_q, out, stream)
+            min_sep_q, out, stream, t_max)
         rc = _lib().ccd_batch(self._h, ctypes.byref(d), ctypes.byref(o),
                               ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:
@@ -318,9 +320,27 @@ class Context:
         self._keep = keep
         return out
 
+    def min_toi(self, toi, out=None, stream=None):
+        """Smallest toi of a device tensor (NaN entries skipped, +inf if none) into a
+        one-element device tensor, asynchronously (the line search's step bound)."""
+        import torch
+        assert toi.is_cuda and toi.dtype == torch.float64 and toi.dim() == 1
+        toi = toi.contiguous()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=toi.device)
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 1
+        if stream is None:
+            stream = torch.cuda.current_stream(toi.device)
+        rc = _lib().ccd_min_toi(self._h, ctypes.c_void_p(toi.data_ptr()), toi.numel(),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise CCDError(rc, "ccd_min_toi")
+        self._keep_min = (toi, out)
+        return out
+
     def batch_host(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
                    min_sep=0.0, literal=False, delta_q=None, max_iter_q=None,
-                   min_sep_q=None) -> BatchResult:
+                   min_sep_q=None, t_max=1.0) -> BatchResult:
         """Blocking batch on host numpy arrays; validates on the host first."""
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
         assert pos.ndim == 2 and pos.shape[0] == 24
@@ -342,7 +362,7 @@ class Context:
                 arr = np.ascontiguousarray(np.asarray(arr, dtype=dt))
                 keep.append(arr)
                 setattr(d, name, arr.ctypes.data)
-        d.params = params(delta, max_iter, min_sep, literal)
+        d.params = params(delta, max_iter, min_sep, literal, t_max)
         d.on_device = 0
         o = ResultSoA(res.toi.ctypes.data, res.t_width.ctypes.data, res.hit.ctypes.data,
                       res.n_checks.ctypes.data, res.status.ctypes.data)
@@ -429,7 +449,8 @@ class Server:
         self._live = {}
 
     def submit(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000, min_sep=0.0,
-               literal=False, nonblocking=False, out: BatchResult | None = None) -> Ticket:
+               literal=False, nonblocking=False, out: BatchResult | None = None,
+               t_max=1.0) -> Ticket:
         """pos: host array float64 [24, n] (numpy, or a pinned torch CPU tensor)."""
         def host(a, dt):
             if hasattr(a, "data_ptr"):
@@ -445,7 +466,7 @@ class Server:
             kind, kptr = host(kind, np.uint8)
             keep.append(kind)
             d.kind = kptr
-        d.params = params(delta, max_iter, min_sep, literal)
+        d.params = params(delta, max_iter, min_sep, literal, t_max)
         d.on_device = 0
         if out is None:
             out = BatchResult(toi=np.empty(n), t_width=np.empty(n), hit=np.empty(n, np.uint8),

@@ -29,6 +29,7 @@ struct ReqEntry {
     double delta;
     int64_t max_iter;
     double min_sep;
+    double t_max;           // time interval [0, t_max]
     uint32_t flags;
     uint32_t default_kind;
     double* toi;
@@ -51,6 +52,7 @@ struct BatchArgs {
     double delta;
     int64_t max_iter;
     double min_sep;
+    double t_max;               // time interval [0, t_max], 0 < t_max <= 1
     uint32_t flags;
     uint32_t default_kind;
     double* toi;

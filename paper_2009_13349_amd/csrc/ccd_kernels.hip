@@ -33,6 +33,7 @@ struct Query {
     double kappa[3];
     double delta;
     double min_sep;
+    double tmax;      // time interval [0, tmax]
     int64_t max_iter;
     int kind;
     bool literal;
@@ -48,7 +49,8 @@ struct State {
 };
 
 struct LevelInfo {
-    double wt, wu, wv;
+    double wt, wu, wv;                  // box widths; wt in s = t / tmax
+    double tmax;                        // time values are tmax * s
     int64_t bt_bits, bu_bits, bv_bits;  // bit patterns of 2^(52-d) per axis (see dyadic())
     double bt_val, bu_val, bv_val;      // 2^(52-d) per axis
     int axis;
@@ -86,6 +88,7 @@ struct QView {
     double delta;
     int64_t max_iter;
     double min_sep;
+    double t_max;
     uint32_t flags;
     double* toi;
     double* t_width;
@@ -99,7 +102,8 @@ __device__ __forceinline__ QView view(const BatchArgs& a, int64_t v) {
     if (!a.reqs) {
         w.pos = a.pos; w.n = a.n; w.q = v; w.kind = a.kind; w.default_kind = a.default_kind;
         w.delta_q = a.delta_q; w.max_iter_q = a.max_iter_q; w.min_sep_q = a.min_sep_q;
-        w.delta = a.delta; w.max_iter = a.max_iter; w.min_sep = a.min_sep; w.flags = a.flags;
+        w.delta = a.delta; w.max_iter = a.max_iter; w.min_sep = a.min_sep; w.t_max = a.t_max;
+        w.flags = a.flags;
         w.toi = a.toi; w.t_width = a.t_width; w.hit = a.hit; w.n_checks = a.n_checks;
         w.status = a.status;
         return w;
@@ -113,7 +117,8 @@ __device__ __forceinline__ QView view(const BatchArgs& a, int64_t v) {
     const ReqEntry& r = a.reqs[lo];
     w.pos = r.pos; w.n = r.n; w.q = v - r.base; w.kind = r.kind; w.default_kind = r.default_kind;
     w.delta_q = nullptr; w.max_iter_q = nullptr; w.min_sep_q = nullptr;
-    w.delta = r.delta; w.max_iter = r.max_iter; w.min_sep = r.min_sep; w.flags = r.flags;
+    w.delta = r.delta; w.max_iter = r.max_iter; w.min_sep = r.min_sep; w.t_max = r.t_max;
+    w.flags = r.flags;
     w.toi = r.toi; w.t_width = r.t_width; w.hit = r.hit; w.n_checks = r.n_checks;
     w.status = r.status;
     return w;
@@ -135,13 +140,17 @@ __device__ __forceinline__ void load_query(const BatchArgs& a, int64_t v, Query&
     Q.max_iter = w.max_iter_q ? w.max_iter_q[q] : w.max_iter;
     Q.min_sep = w.min_sep_q ? w.min_sep_q[q] : w.min_sep;
     Q.literal = (w.flags & kFlagLiteral) != 0;
+    Q.tmax = w.t_max;
     double gmin;
     filter_eps(Q.kind, Q.X, Q.min_sep, Q.eps, &gmin);
     valid = (Q.kind == kVF || Q.kind == kEE) && query_valid(Q.X, Q.delta, Q.max_iter, Q.min_sep, gmin);
 }
 
-__device__ __forceinline__ LevelInfo level_info(const double kappa[3], const int32_t d[3]) {
+// The split rule compares w(I_t) kappa_t with w(I_t) = tmax * 2^-dt (exact).
+__device__ __forceinline__ LevelInfo level_info(const double kappa[3], const int32_t d[3],
+                                                double tmax) {
     LevelInfo L;
+    L.tmax = tmax;
     L.wt = pow2neg(d[0]);
     L.wu = pow2neg(d[1]);
     L.wv = pow2neg(d[2]);
@@ -151,7 +160,7 @@ __device__ __forceinline__ LevelInfo level_info(const double kappa[3], const int
     L.bt_val = __longlong_as_double(L.bt_bits);
     L.bu_val = __longlong_as_double(L.bu_bits);
     L.bv_val = __longlong_as_double(L.bv_bits);
-    L.axis = split_axis(kappa, L.wt, L.wu, L.wv);
+    L.axis = split_axis(kappa, tmax * L.wt, L.wu, L.wv);
     L.dcap = d[L.axis] >= kMaxDepth;
     return L;
 }
@@ -202,7 +211,7 @@ __device__ __forceinline__ void acc_merge(Acc& A, const Acc& B) {
 __device__ __forceinline__ bool need_rank(const Acc& A, const State& S, bool literal,
                                           int64_t max_iter, const LevelInfo& L) {
     if (!(A.fflags & 1u)) return false;
-    const double tf = (double)A.ft * L.wt;
+    const double tf = L.tmax * ((double)A.ft * L.wt);
     const bool carry_ret = !literal && S.tpend <= tf;
     const bool cap_possible = S.N + S.cnt >= (uint64_t)max_iter;
     return carry_ret || cap_possible || (A.fflags & 2u);
@@ -216,7 +225,7 @@ __device__ __forceinline__ Outcome decide_first(const Acc& A, const State& S, bo
     Outcome O;
     O.finish = true;
     const uint64_t mI = (uint64_t)max_iter;
-    const double tf = (double)A.ft * L.wt;
+    const double tf = L.tmax * ((double)A.ft * L.wt);
     const bool cap_possible = S.N + S.cnt >= mI;
     const uint64_t nf = S.N + rf + 1;
     if (!literal && S.tpend <= tf) {
@@ -224,11 +233,11 @@ __device__ __forceinline__ Outcome decide_first(const Acc& A, const State& S, bo
         return O;
     }
     if (cap_possible && nf >= mI) {
-        O.toi = tf; O.tw = L.wt; O.n = mI; O.st = kStCap;
+        O.toi = tf; O.tw = L.tmax * L.wt; O.n = mI; O.st = kStCap;
         return O;
     }
     if (A.fflags & 2u) {
-        O.toi = tf; O.tw = L.wt; O.n = nf; O.st = (A.fflags & 4u) ? 0 : kStDepth;
+        O.toi = tf; O.tw = L.tmax * L.wt; O.n = nf; O.st = (A.fflags & 4u) ? 0 : kStDepth;
         return O;
     }
     O.finish = false;
@@ -257,11 +266,11 @@ __device__ __forceinline__ Outcome decide(const Acc& A, const State& S, bool lit
     }
     O = decide_first(A, S, literal, max_iter, L, rf);
     if (O.finish) return O;
-    const double tf = (double)A.ft * L.wt;
+    const double tf = L.tmax * ((double)A.ft * L.wt);
     const bool cap_possible = S.N + S.cnt >= mI;
     O.finish = true;
     if (cap_possible && S.N + rm + 1 >= mI) {
-        O.toi = tf; O.tw = L.wt; O.n = mI; O.st = kStCap;
+        O.toi = tf; O.tw = L.tmax * L.wt; O.n = mI; O.st = kStCap;
         return O;
     }
     O.finish = false;
@@ -272,10 +281,10 @@ __device__ __forceinline__ Outcome decide(const Acc& A, const State& S, bool lit
 __device__ __forceinline__ void advance(State& S, const Acc& A, bool literal, const LevelInfo& L,
                                         uint32_t next_cnt) {
     if (!literal && A.thave) {
-        const double tm = (double)A.tm * L.wt;
+        const double tm = L.tmax * ((double)A.tm * L.wt);
         if (tm < S.tpend) {
             S.tpend = tm;
-            S.wpend = L.wt;
+            S.wpend = L.tmax * L.wt;
         }
     }
     S.N += S.cnt;
@@ -308,10 +317,11 @@ template <int KIND>
 __device__ __forceinline__ CheckResult check_key(const Query& Q, const LevelInfo& L, uint64_t bt,
                                                  uint64_t bu, uint64_t bv, bool root,
                                                  double kappa_out[3]) {
-    const double t0 = dyadic(bt, L.bt_bits, L.bt_val);
+    const double s0 = dyadic(bt, L.bt_bits, L.bt_val);
     const double u0 = dyadic(bu, L.bu_bits, L.bu_val);
     const double v0 = dyadic(bv, L.bv_bits, L.bv_val);
-    return box_check<KIND>(Q.X, t0, t0 + L.wt, u0, u0 + L.wu, v0, v0 + L.wv, Q.eps, Q.min_sep,
+    return box_check<KIND>(Q.X, L.tmax * s0, L.tmax * (s0 + L.wt), u0, u0 + L.wu, v0, v0 + L.wv,
+                           Q.eps, Q.min_sep,
                            Q.delta, root, kappa_out);
 }
 
@@ -465,15 +475,18 @@ __global__ __launch_bounds__(1024) void k_root(BatchArgs a, int64_t* order) {
             write_invalid(a, q);
         } else {
             double kap[3];
+            // the root box [0, tmax] x [0,1]^2 (time values tmax * 0 and tmax * 1)
+            const double t1 = Q.tmax * 1.0;
             const CheckResult R = Q.kind == kEE
-                ? box_check<kEE>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap)
-                : box_check<kVF>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap);
+                ? box_check<kEE>(Q.X, 0.0, t1, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap)
+                : box_check<kVF>(Q.X, 0.0, t1, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta, false, kap);
             // Alg. 2's decision on a one-box level 0
             State S;
             S.N = 0; S.tpend = INFINITY; S.wpend = 0.0; S.level = 0;
             S.d[0] = S.d[1] = S.d[2] = 0; S.cnt = 1;
             LevelInfo L;
             L.wt = L.wu = L.wv = 1.0;
+            L.tmax = Q.tmax;
             Acc A;
             acc_init(A);
             if (R.collide) acc_add(A, 0, 0, 0, R.small, R.small);
@@ -513,6 +526,28 @@ __global__ __launch_bounds__(1024) void k_root(BatchArgs a, int64_t* order) {
     const uint64_t lt = lanemask_lt();
     if (vf) order[base[0] + ov + __popcll(mv & lt)] = q;
     if (ee) order[a.n - 1 - (int64_t)(base[1] + oe + __popcll(me & lt))] = q;
+}
+
+// Smallest toi of a batch: the line search bounds its step by the earliest time
+// of impact (alpha = min over the candidates, Sec. 6).  toi values are +0..1,
+// +inf or NaN (invalid queries, skipped); the bit patterns of non-negative
+// doubles order like their values, so an integer atomic min gives the result.
+__global__ void k_min_toi_init(unsigned long long* out) {
+    if (threadIdx.x == 0) *out = (unsigned long long)__double_as_longlong(INFINITY);
+}
+
+__global__ __launch_bounds__(256) void k_min_toi(const double* toi, int64_t n,
+                                                 unsigned long long* out) {
+    double m = INFINITY;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = toi[i];
+        if (v < m) m = v;  // false for NaN
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+    if (__lane_id() == 0 && m < INFINITY)
+        atomicMin(out, (unsigned long long)__double_as_longlong(m));
 }
 
 // Resets the counters at the start of a batch (a kernel, so that it can sit
@@ -606,8 +641,8 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 next_cnt = 0;
                 cur = 0;
                 acc_init(A);
-                Q.kappa[0] = Q.kappa[1] = Q.kappa[2] = 0.0;  // set by the level-0 check
-                L = level_info(Q.kappa, S.d);
+                Q.kappa[0] = Q.kappa[1] = Q.kappa[2] = 0.0;  // set at the level-0 check
+                L = level_info(Q.kappa, S.d, Q.tmax);
             }
         }
         if (q < 0) continue;
@@ -620,8 +655,19 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             bu = ar[arena_idx(K, cur, idx, 1)];
             bv = ar[arena_idx(K, cur, idx, 2)];
         }
-        const CheckResult R = check_any(Q, L, bt, bu, bv, root, Q.kappa);
-        if (root) L = level_info(Q.kappa, S.d);
+        // kappa (eq. kappas) comes from the corners of [0,1]^3: the level-0 check
+        // produces it when the time interval is the full one
+        const bool fused = root && Q.tmax == 1.0;
+        if (root && !fused) {
+            if (Q.kind == kEE)
+                (void)box_check<kEE>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
+                                     true, Q.kappa);
+            else
+                (void)box_check<kVF>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
+                                     true, Q.kappa);
+        }
+        const CheckResult R = check_any(Q, L, bt, bu, bv, fused, Q.kappa);
+        if (root) L = level_info(Q.kappa, S.d, Q.tmax);
         nchk[Q.kind] += 1;
         if (R.collide) {
             const bool term = R.small || L.dcap;
@@ -672,7 +718,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             idx = 0;
             next_cnt = 0;
             acc_init(A);
-            L = level_info(Q.kappa, S.d);
+            L = level_info(Q.kappa, S.d, Q.tmax);
             promote = PERSISTENT && S.N + S.cnt > c.budget;
         }
         if (promote) {
@@ -1038,13 +1084,16 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         if (!B.act[0]) return;
         if (kPair) {
             double tv[3], uv[3], vv[3];
-            tv[0] = B.t0[0]; tv[1] = tv[0] + L.wt; tv[2] = tv[1] + L.wt;
+            // time values tmax * s at s0, s0 + w, s0 + 2w (the sums are exact)
+            tv[0] = L.tmax * B.t0[0];
+            tv[1] = L.tmax * (B.t0[0] + L.wt);
+            tv[2] = L.tmax * ((B.t0[0] + L.wt) + L.wt);
             uv[0] = B.u0[0]; uv[1] = uv[0] + L.wu; uv[2] = uv[1] + L.wu;
             vv[0] = B.v0[0]; vv[1] = vv[0] + L.wv; vv[2] = vv[1] + L.wv;
             check_pair_lds<KIND, SPLIT>(sh.Xs, sh.Es, tv, uv, vv, min_sep, delta, B.act[1],
                                         B.R[0], B.R[1]);
         } else {
-            B.R[0] = check_box_lds<KIND>(sh.Xs, sh.Es, B.t0[0], B.t0[0] + L.wt, B.u0[0],
+            B.R[0] = check_box_lds<KIND>(sh.Xs, sh.Es, L.tmax * B.t0[0], L.tmax * (B.t0[0] + L.wt), B.u0[0],
                                          B.u0[0] + L.wu, B.v0[0], B.v0[0] + L.wv, min_sep, delta);
         }
     };
@@ -1166,7 +1215,8 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
             bool ends = false;
 #pragma unroll
             for (int b = 0; b < 2; ++b)
-                ends = ends || (col[b] && (term[b] || cap_level || (!literal && S.tpend <= B.t0[b])));
+                ends = ends || (col[b] && (term[b] || cap_level ||
+                                           (!literal && S.tpend <= L.tmax * B.t0[b])));
             if (__ballot(ends) != 0) {
                 tried = true;
                 KeyAcc F = K;
@@ -1378,8 +1428,9 @@ __device__ __forceinline__ void run_rank(GroupShared<W>& sh, const uint64_t* ct,
 template <int W, int KIND>
 __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
                                             uint64_t* base, const Record& h, const double kappa[3],
-                                            double delta, double min_sep, int64_t max_iter,
-                                            bool literal, uint64_t& nchk, uint64_t& slots) {
+                                            double delta, double min_sep, double tmax,
+                                            int64_t max_iter, bool literal, uint64_t& nchk,
+                                            uint64_t& slots) {
     constexpr int T = 64 * W;
     const int tid = threadIdx.x;
     const int64_t cap = g.capacity;
@@ -1391,7 +1442,7 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
     int pa = 0;
     int64_t words = h.cnt;
     while (true) {
-        LevelInfo L = level_info(kappa, S.d);
+        LevelInfo L = level_info(kappa, S.d, tmax);
         // equal in every lane: keep the level's description in scalar registers
         L.axis = (int)uni32((uint32_t)L.axis);
         L.dcap = uni32(L.dcap ? 1u : 0u) != 0;
@@ -1504,6 +1555,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         const double delta = unif64(qv.delta_q ? qv.delta_q[q] : qv.delta);
         const int64_t max_iter = uni64s(qv.max_iter_q ? qv.max_iter_q[q] : qv.max_iter);
         const double min_sep = unif64(qv.min_sep_q ? qv.min_sep_q[q] : qv.min_sep);
+        const double tmax = unif64(qv.t_max);
         const bool literal = (uni32(qv.flags) & kFlagLiteral) != 0;
         if (tid < 24) {
             const int c = tid % 3, k = tid / 3;
@@ -1536,9 +1588,11 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         for (int k = 0; k < 3; ++k) kappa[k] = unif64(kappa[k]);
         __syncthreads();
         if (kind == kEE)
-            group_query<W, kEE>(a, g, sh, base, h, kappa, delta, min_sep, max_iter, literal, nchk[1], slots);
+            group_query<W, kEE>(a, g, sh, base, h, kappa, delta, min_sep, tmax, max_iter, literal,
+                               nchk[1], slots);
         else
-            group_query<W, kVF>(a, g, sh, base, h, kappa, delta, min_sep, max_iter, literal, nchk[0], slots);
+            group_query<W, kVF>(a, g, sh, base, h, kappa, delta, min_sep, tmax, max_iter, literal,
+                               nchk[0], slots);
         __syncthreads();
     }
     if (tid == 0) {

@@ -29,6 +29,8 @@ __global__ void k_lane(BatchArgs a, LaneCfg c);
 template <int W, int OCC>
 __global__ void k_group(BatchArgs a, GroupCfg g);
 __global__ void k_root(BatchArgs a, int64_t* order);
+__global__ void k_min_toi_init(unsigned long long* out);
+__global__ void k_min_toi(const double* toi, int64_t n, unsigned long long* out);
 __global__ void k_reset(unsigned long long* counters);
 }  // namespace ccd
 
@@ -127,8 +129,10 @@ void clamp_tuning(ccd_tuning& t) {
     t.group_occupancy = std::min(4, std::max(1, t.group_occupancy));
 }
 
+// 0 < t_max <= 1 (false for NaN), no unknown flags.
 bool params_ok(const ccd_params& p) {
-    return p.t_max == 1.0 && p.reserved == 0 && (p.flags & ~CCD_FLAG_LITERAL) == 0;
+    return p.t_max > 0.0 && p.t_max <= 1.0 && p.reserved == 0 &&
+           (p.flags & ~CCD_FLAG_LITERAL) == 0;
 }
 
 // Host copy of the device-side query validation (same rule, same arithmetic).
@@ -603,6 +607,7 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
     a.delta = d->params.delta;
     a.max_iter = d->params.max_iter;
     a.min_sep = d->params.min_sep;
+    a.t_max = d->params.t_max;
     a.flags = d->params.flags;
     a.default_kind = d->default_kind;
 
@@ -880,6 +885,27 @@ int ccd_tuning_cache_load(ccd_context* ctx, const char* path, const char* key) {
     if (!found) return CCD_EAGAIN;
     clamp_tuning(t);
     ctx->tune = t;
+    return CCD_OK;
+}
+
+int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, void* stream) {
+    if (!ctx || n < 0 || !out || (n > 0 && !toi)) {
+        set_last_error("ccd_min_toi: null pointer or negative n");
+        return CCD_EINVAL;
+    }
+    if (((uintptr_t)out & 7) != 0) {
+        set_last_error("ccd_min_toi: out is not 8-byte aligned");
+        return CCD_EINVAL;
+    }
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
+    hipLaunchKernelGGL(k_min_toi_init, dim3(1), dim3(64), 0, s, o);
+    if (n > 0) {
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)ctx->num_cu * 8);
+        hipLaunchKernelGGL(k_min_toi, dim3((unsigned)blocks), dim3(256), 0, s, toi, n, o);
+    }
+    if (!record_hip(hipGetLastError(), "ccd_min_toi launch")) return CCD_EDEVICE;
     return CCD_OK;
 }
 

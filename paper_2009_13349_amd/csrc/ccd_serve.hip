@@ -277,6 +277,7 @@ void launch_slot(ccd_server* s, Slot& sl) {
         e.delta = r->params.delta;
         e.max_iter = r->params.max_iter;
         e.min_sep = r->params.min_sep;
+        e.t_max = r->params.t_max;
         e.flags = r->params.flags;
         e.default_kind = r->default_kind;
         e.toi = r->d_toi;
@@ -372,7 +373,8 @@ bool desc_valid_host(const ccd_batch_desc* d, const ccd_result_soa* out) {
     if (d->delta_q || d->max_iter_q || d->min_sep_q) return false;  // per-request scalars only
     if (d->default_kind > 1) return false;
     const ccd_params& p = d->params;
-    if (!(p.t_max == 1.0) || p.reserved || (p.flags & ~CCD_FLAG_LITERAL)) return false;
+    if (!(p.t_max > 0.0 && p.t_max <= 1.0) || p.reserved || (p.flags & ~CCD_FLAG_LITERAL))
+        return false;
     if (!out->toi || !out->t_width || !out->hit || !out->n_checks || !out->status) return false;
     const int64_t n = d->n;
     for (int64_t q = 0; q < n; ++q) {

@@ -1,0 +1,179 @@
+"""GPU <-> oracle parity of the shortened time interval [0, t_max] (the line
+search's change to Alg. 2's initial interval, Sec. 6) and of the batch-wide
+smallest toi used to bound the step length.  Same bar as the other parity
+tests: every output bit-identical."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_13349_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("toi", "t_width", "hit", "n_checks", "status")
+T_MAXES = [0.5, 0.3, 0.999, 1e-3, 0.7734375, 2.0 ** -30]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ccdmod():
+    from paper_2009_13349_amd import ccd
+    ccd.load()
+    return ccd
+
+
+@pytest.fixture()
+def ctx(ccdmod, torch_dev):
+    c = ccdmod.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, torch_dev, w, engine=0, **kw):
+    torch, dev = torch_dev
+    ctx.set_engine(engine)
+    pos = torch.from_numpy(np.ascontiguousarray(w["pos"])).to(dev)
+    kind = torch.from_numpy(np.ascontiguousarray(w["kind"])).to(dev)
+    r = ctx.batch_device(pos, kind, **kw)
+    torch.cuda.synchronize()
+    out = {k: getattr(r, k).cpu().numpy() for k in FIELDS}
+    out["n_checks"] = out["n_checks"].astype(np.uint64)
+    return out, r
+
+
+def assert_same(got, ref, what):
+    for k in FIELDS:
+        if k in ("toi", "t_width"):
+            g = np.ascontiguousarray(got[k], dtype=np.float64).view(np.int64)
+            r = np.ascontiguousarray(ref[k], dtype=np.float64).view(np.int64)
+        else:
+            g = np.asarray(got[k]).astype(np.int64)
+            r = np.asarray(ref[k]).astype(np.int64)
+        bad = np.nonzero(g != r)[0]
+        assert len(bad) == 0, (f"{what}: {k} differs at {len(bad)} queries, first {bad[:5].tolist()}: "
+                               f"gpu {np.asarray(got[k])[bad[:5]]} oracle {np.asarray(ref[k])[bad[:5]]}")
+
+
+@pytest.mark.parametrize("t_max", T_MAXES)
+def test_tmax_parity(ctx, torch_dev, t_max):
+    w = W.concat([W.uniform_vf(1500, seed=51), W.edge_edge_mixed(1500, seed=52),
+                  W.subset(W.simulation_mixed(20_000, seed=53), np.arange(0, 20_000, 5))])
+    ref = oracle.solve_batch(w["pos"], w["kind"], max_iter=200_000, t_max=t_max)
+    assert np.all(np.where(ref["hit"] == 1, ref["toi"] <= t_max, True))
+    for engine in (0, 1):
+        got, _ = run_gpu(ctx, torch_dev, w, engine, max_iter=200_000, t_max=t_max)
+        assert_same(got, ref, f"t_max {t_max} engine {engine}")
+
+
+@pytest.mark.parametrize("t_max", [0.5, 0.3])
+def test_tmax_parity_through_group_engines(ctx, torch_dev, t_max):
+    """Every query past its root level goes through the group engines (one-check
+    lane budget), in default and literal modes, with one- and eight-wave
+    blocks, and with m_I at small values."""
+    w = W.concat([W.uniform_vf(600, seed=54), W.edge_edge_mixed(600, seed=55)])
+    n = w["pos"].shape[1]
+    mq = np.random.default_rng(5).integers(1, 3000, n).astype(np.int64)
+    torch, dev = torch_dev
+    for literal in (False, True):
+        ref = oracle.solve_batch(w["pos"], w["kind"], max_iter=mq, literal=literal, t_max=t_max)
+        for tune in ({"lane_capacity": 8, "lane_budget": 1},
+                     {"lane_capacity": 8, "lane_budget": 1, "group_waves": 8}):
+            ctx.set_tuning(**tune)
+            got, _ = run_gpu(ctx, torch_dev, w, 0, literal=literal, t_max=t_max,
+                             max_iter_q=torch.from_numpy(mq).to(dev))
+            assert_same(got, ref, f"t_max {t_max} literal {literal} tuning {tune}")
+
+
+def test_tmax_single_queries(ccdmod, torch_dev):
+    w = W.concat([W.uniform_vf(40, seed=56), W.edge_edge_mixed(40, seed=57)])
+    for i in range(w["pos"].shape[1]):
+        X = w["pos"][:, i]
+        kind = int(w["kind"][i])
+        for t_max in (0.5, 0.123):
+            fn = ccdmod.vf if kind == 0 else ccdmod.ee
+            g = fn(X, 1e-6, 100_000, 0.0, t_max=t_max)
+            r = oracle.solve(kind, X, 1e-6, 100_000, 0.0, t_max=t_max)
+            assert (g.toi, g.t_width, g.n_checks, g.hit, g.status) == \
+                (r.toi, r.t_width, r.n_checks, r.hit, r.status), (i, t_max)
+
+
+@pytest.mark.parametrize("t_max", [0.0, -0.5, 1.5, float("nan"), float("inf")])
+def test_invalid_tmax_rejected(ccdmod, ctx, torch_dev, t_max):
+    torch, dev = torch_dev
+    w = W.uniform_vf(16, seed=58)
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    with pytest.raises(ccdmod.CCDError) as e:
+        ctx.batch_device(pos, t_max=t_max)
+    assert e.value.code == ccdmod.EINVAL
+    with pytest.raises(ccdmod.CCDError):
+        ccdmod.vf(w["pos"][:, 0], t_max=t_max)
+
+
+def test_min_toi(ccdmod, ctx, torch_dev):
+    torch, dev = torch_dev
+    w = W.uniform_vf(4000, seed=59)
+    dq = np.full(4000, 1e-6)
+    dq[::97] = -1.0  # invalid queries: toi NaN, skipped by the reduction
+    for t_max in (1.0, 0.4):
+        _, r = run_gpu(ctx, torch_dev, w, 0, delta_q=torch.from_numpy(dq).to(dev), t_max=t_max)
+        out = ctx.min_toi(r.toi)
+        torch.cuda.synchronize()
+        toi = r.toi.cpu().numpy()
+        assert np.isnan(toi[::97]).all()
+        expect = np.nanmin(toi)
+        assert out.item() == expect and expect <= t_max
+    # all misses, and the empty batch: +inf
+    miss = torch.full((1000,), math.inf, dtype=torch.float64, device=dev)
+    assert ctx.min_toi(miss).item() == math.inf
+    assert ctx.min_toi(miss[:0]).item() == math.inf
+    nan = torch.full((10,), math.nan, dtype=torch.float64, device=dev)
+    assert ctx.min_toi(nan).item() == math.inf
+    one = miss.clone()
+    one[777] = 0.0
+    assert ctx.min_toi(one).item() == 0.0
+
+
+def test_line_search_step(ccdmod, ctx, torch_dev):
+    """Alg. 4's CCD loop on one batch: alpha = min(alpha, toi) with the interval
+    shortened to the current alpha; the step never grows and every returned
+    toi is within [0, alpha]."""
+    torch, dev = torch_dev
+    w = W.concat([W.uniform_vf(2000, seed=60), W.edge_edge_mixed(2000, seed=61)])
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    kind = torch.from_numpy(w["kind"]).to(dev)
+    alpha = 1.0
+    for _ in range(3):
+        r = ctx.batch_device(pos, kind, max_iter=100_000, t_max=alpha)
+        m = ctx.min_toi(r.toi).item()
+        toi = r.toi.cpu().numpy()
+        fin = np.isfinite(toi)
+        assert np.all(toi[fin] <= alpha)
+        ref = oracle.solve_batch(w["pos"], w["kind"], max_iter=100_000, t_max=alpha)
+        assert np.array_equal(toi.view(np.int64), ref["toi"].view(np.int64))
+        new = min(alpha, m)
+        assert new <= alpha
+        if new == alpha or new == 0.0:
+            break
+        alpha = new
+
+
+def test_tmax_serving(ccdmod, torch_dev):
+    """Requests with different t_max share launches; each gets its own interval."""
+    w = W.concat([W.uniform_vf(700, seed=62), W.edge_edge_mixed(700, seed=63)])
+    with ccdmod.Server(pool_bytes=64 << 20, streams=2, scratch_bytes=4 << 30) as srv:
+        tickets = [(t_max, srv.submit(w["pos"], w["kind"], max_iter=100_000, t_max=t_max))
+                   for t_max in (1.0, 0.5, 0.2)]
+        for t_max, t in tickets:
+            res = srv.wait(t)
+            ref = oracle.solve_batch(w["pos"], w["kind"], max_iter=100_000, t_max=t_max)
+            got = {k: getattr(res, k) for k in FIELDS}
+            assert_same(got, ref, f"serving t_max {t_max}")
