@@ -546,8 +546,15 @@ __global__ __launch_bounds__(256) void k_min_toi(const double* toi, int64_t n,
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
-    if (__lane_id() == 0 && m < INFINITY)
-        atomicMin(out, (unsigned long long)__double_as_longlong(m));
+    // one atomic per block
+    __shared__ double wmin[4];
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) wmin[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        if (m < INFINITY) atomicMin(out, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 // Resets the counters at the start of a batch (a kernel, so that it can sit

@@ -106,7 +106,7 @@ int set_device(int dev) {
 
 void default_tuning(ccd_tuning& t, int num_cu) {
     t.lane_waves_per_cu = 8;
-    t.lane_capacity = 32;
+    t.lane_capacity = 16;
     t.lane_budget = 256;
     t.group_waves = 1;
     t.group_count = num_cu * 12;
@@ -902,7 +902,7 @@ int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, voi
     unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
     hipLaunchKernelGGL(k_min_toi_init, dim3(1), dim3(64), 0, s, o);
     if (n > 0) {
-        const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)ctx->num_cu * 8);
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)ctx->num_cu * 2);
         hipLaunchKernelGGL(k_min_toi, dim3((unsigned)blocks), dim3(256), 0, s, toi, n, o);
     }
     if (!record_hip(hipGetLastError(), "ccd_min_toi launch")) return CCD_EDEVICE;
