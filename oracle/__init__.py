@@ -85,10 +85,16 @@ def lib():
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                         ctypes.POINTER(OracleResult)]
         L.oracle_solve_tmax.restype = ctypes.c_int
+        L.oracle_solve_full.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int64,
+                                        ctypes.c_double, ctypes.c_double, _D, ctypes.c_int,
+                                        ctypes.POINTER(OracleResult)]
+        L.oracle_solve_full.restype = ctypes.c_int
+        L.oracle_filter_gamma.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D]
+        L.oracle_filter_gamma.restype = None
         L.oracle_solve_batch.argtypes = [
             ctypes.c_int64, _D, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
             _D, ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
-            _D, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _D, ctypes.c_double, ctypes.c_double, _D, ctypes.c_int,
             _D, _D, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint64),
             ctypes.POINTER(ctypes.c_uint8)]
         L.oracle_solve_batch.restype = ctypes.c_int64
@@ -111,6 +117,14 @@ def F(kind: int, X, t: float, u: float, v: float) -> np.ndarray:
     out = np.zeros(3)
     lib().oracle_F(kind, _dptr(X), t, u, v, _dptr(out))
     return out
+
+
+def filter_eps_gamma(kind: int, gamma, min_sep: float = 0.0) -> np.ndarray:
+    """eq. ccd-error / msccd-error for a given gamma per axis."""
+    g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    eps = np.empty(3)
+    lib().oracle_filter_gamma(kind, _dptr(g), float(min_sep), _dptr(eps))
+    return eps
 
 
 def filter_eps(kind: int, X, min_sep: float = 0.0) -> np.ndarray:
@@ -152,20 +166,23 @@ def validate(X, delta: float, max_iter: int, min_sep: float = 0.0) -> bool:
 
 
 def solve(kind: int, X, delta: float = 1e-6, max_iter: int = 1_000_000, min_sep: float = 0.0,
-          literal: bool = False, t_max: float = 1.0) -> OracleResult:
+          literal: bool = False, t_max: float = 1.0, gamma=None) -> OracleResult:
     """Algorithm 2 on one query over I = [0, t_max] x [0,1]^2; raises ValueError on
-    invalid input.  The result's box keeps the time axis normalized (t / t_max)."""
+    invalid input.  gamma: scene-wide gamma per axis (3 values) or None.  The
+    result's box keeps the time axis normalized (t / t_max)."""
     X = _as_x(X)
     r = OracleResult()
-    rc = lib().oracle_solve_tmax(kind, _dptr(X), delta, int(max_iter), min_sep, float(t_max),
-                                 int(literal), ctypes.byref(r))
+    g = None if gamma is None else np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    rc = lib().oracle_solve_full(kind, _dptr(X), delta, int(max_iter), min_sep, float(t_max),
+                                 None if g is None else _dptr(g), int(literal), ctypes.byref(r))
     if rc != 0:
         raise ValueError("invalid CCD query")
     return r
 
 
 def solve_batch(pos: np.ndarray, kind=None, default_kind: int = 0, delta=1e-6,
-                max_iter=1_000_000, min_sep=0.0, literal: bool = False, t_max: float = 1.0):
+                max_iter=1_000_000, min_sep=0.0, literal: bool = False, t_max: float = 1.0,
+                gamma=None):
     """Batch over SoA positions pos[24, n]. delta/max_iter/min_sep may be scalars
     or per-query arrays. Returns a dict of numpy arrays."""
     pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
@@ -181,6 +198,7 @@ def solve_batch(pos: np.ndarray, kind=None, default_kind: int = 0, delta=1e-6,
     dq, ds = _arr(delta, np.float64)
     mq, ms_ = _arr(max_iter, np.int64)
     sq, ss = _arr(min_sep, np.float64)
+    g = None if gamma is None else np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
     toi = np.empty(n)
     tw = np.empty(n)
     hit = np.empty(n, np.uint8)
@@ -191,7 +209,8 @@ def solve_batch(pos: np.ndarray, kind=None, default_kind: int = 0, delta=1e-6,
         n, _dptr(pos), None if kind_a is None else kind_a.ctypes.data_as(u8), default_kind,
         None if dq is None else _dptr(dq), float(ds),
         None if mq is None else mq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(ms_),
-        None if sq is None else _dptr(sq), float(ss), float(t_max), int(literal),
+        None if sq is None else _dptr(sq), float(ss), float(t_max),
+        None if g is None else _dptr(g), int(literal),
         _dptr(toi), _dptr(tw), hit.ctypes.data_as(u8),
         nc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), st.ctypes.data_as(u8))
     return {"toi": toi, "t_width": tw, "hit": hit, "n_checks": nc, "status": st,

@@ -40,6 +40,10 @@
 //     s = t / t_max; a box's time endpoints are fl(t_max * s) and its width is
 //     w(I_t) = t_max * w(I_s) (exact).  kappa keeps eq. kappas (corners at
 //     t = 0 and t = 1: a per-unit slope).  ORDER compares s, which orders like t.
+//   * scene-wide filter (Sec. 6: eps from the maximum over all the vertices of
+//     the scene): an optional gamma per axis replaces the query's own; it must
+//     be at least the query's gamma (else the filter's bound does not cover the
+//     query, which is then invalid), and d < min_c gamma_c uses it.
 #include <cmath>
 #include <cstdint>
 #include <queue>
@@ -125,6 +129,14 @@ void oracle_filter(int kind, const double X[24], double min_sep, double eps[3]) 
         }
         eps[c] = ((K * g) * g) * g;
     }
+}
+
+// eq. ccd-error / eq. msccd-error with a given gamma per axis.
+void oracle_filter_gamma(int kind, const double gamma[3], double min_sep, double eps[3]) {
+    double K;
+    if (min_sep > 0.0) K = (kind == ORACLE_EE) ? 0x1p-47 : 0x1.1p-47;
+    else               K = (kind == ORACLE_EE) ? 0x1.cp-48 : 0x1.ep-48;
+    for (int c = 0; c < 3; ++c) eps[c] = ((K * gamma[c]) * gamma[c]) * gamma[c];
 }
 
 static double gamma_min(const double X[24]) {
@@ -266,15 +278,35 @@ static void fill_result(oracle_result* out, double toi, double tw, uint64_t n, i
 }
 
 // Alg. 2 on I = [0, t_max] x [0,1]^2.  Box.t holds the normalized time
-// interval (s); time values are fl(t_max * s).
-int oracle_solve_tmax(int kind, const double X[24], double delta, int64_t max_iter,
-                      double min_sep, double t_max, int literal, oracle_result* out) {
+// interval (s); time values are fl(t_max * s).  gamma: scene-wide gamma per
+// axis, or NULL for the query's own.
+int oracle_solve_full(int kind, const double X[24], double delta, int64_t max_iter,
+                      double min_sep, double t_max, const double* gamma, int literal,
+                      oracle_result* out) {
     if (kind != ORACLE_VF && kind != ORACLE_EE) return ORACLE_EINVAL;
-    if (oracle_validate(X, delta, max_iter, min_sep) != ORACLE_OK) return ORACLE_EINVAL;
     if (!(t_max > 0.0 && t_max <= 1.0)) return ORACLE_EINVAL;
-
     double eps[3], kappa[3];
-    oracle_filter(kind, X, min_sep, eps);
+    if (gamma) {
+        // the query's own validity with min_sep checked against the scene gamma
+        if (oracle_validate(X, delta, max_iter, 0.0) != ORACLE_OK) return ORACLE_EINVAL;
+        if (!(min_sep >= 0.0) || !std::isfinite(min_sep)) return ORACLE_EINVAL;
+        double gmin = INFINITY;
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(gamma[c])) return ORACLE_EINVAL;
+            double g = 1.0;
+            for (int k = 0; k < 8; ++k) {
+                double a = std::fabs(X[3 * k + c]);
+                if (a > g) g = a;
+            }
+            if (!(gamma[c] >= g)) return ORACLE_EINVAL;
+            if (gamma[c] < gmin) gmin = gamma[c];
+        }
+        if (!(min_sep < gmin)) return ORACLE_EINVAL;
+        oracle_filter_gamma(kind, gamma, min_sep, eps);
+    } else {
+        if (oracle_validate(X, delta, max_iter, min_sep) != ORACLE_OK) return ORACLE_EINVAL;
+        oracle_filter(kind, X, min_sep, eps);
+    }
     oracle_kappa(kind, X, kappa);
 
     std::priority_queue<Box, std::vector<Box>, After> Q;
@@ -353,9 +385,14 @@ int oracle_solve_tmax(int kind, const double X[24], double delta, int64_t max_it
     return ORACLE_OK;
 }
 
+int oracle_solve_tmax(int kind, const double X[24], double delta, int64_t max_iter,
+                      double min_sep, double t_max, int literal, oracle_result* out) {
+    return oracle_solve_full(kind, X, delta, max_iter, min_sep, t_max, nullptr, literal, out);
+}
+
 int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, double min_sep,
                  int literal, oracle_result* out) {
-    return oracle_solve_tmax(kind, X, delta, max_iter, min_sep, 1.0, literal, out);
+    return oracle_solve_full(kind, X, delta, max_iter, min_sep, 1.0, nullptr, literal, out);
 }
 
 // Batch driver over the structure-of-arrays layout pos[(3k+c)*n + q]. Per-query
@@ -364,8 +401,8 @@ int oracle_solve(int kind, const double X[24], double delta, int64_t max_iter, d
 int64_t oracle_solve_batch(int64_t n, const double* pos, const uint8_t* kind, int default_kind,
                            const double* delta_q, double delta, const int64_t* max_iter_q,
                            int64_t max_iter, const double* min_sep_q, double min_sep, double t_max,
-                           int literal, double* toi, double* t_width, uint8_t* hit,
-                           uint64_t* n_checks, uint8_t* status) {
+                           const double* gamma, int literal, double* toi, double* t_width,
+                           uint8_t* hit, uint64_t* n_checks, uint8_t* status) {
     int64_t bad = 0;
     for (int64_t q = 0; q < n; ++q) {
         double X[24];
@@ -375,7 +412,7 @@ int64_t oracle_solve_batch(int64_t n, const double* pos, const uint8_t* kind, in
         int64_t mi = max_iter_q ? max_iter_q[q] : max_iter;
         double ms = min_sep_q ? min_sep_q[q] : min_sep;
         oracle_result r;
-        if (oracle_solve_tmax(k, X, dl, mi, ms, t_max, literal, &r) != ORACLE_OK) {
+        if (oracle_solve_full(k, X, dl, mi, ms, t_max, gamma, literal, &r) != ORACLE_OK) {
             ++bad;
             toi[q] = NAN; t_width[q] = NAN; hit[q] = 0; n_checks[q] = 0; status[q] = 0xFF;
             continue;
