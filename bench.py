@@ -188,6 +188,36 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 32, loa
             "latency": "scheduled arrival -> results in the caller's host arrays"}
 
 
+def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
+    """Candidate pairs over shared vertex arrays with a scene-wide filter (the
+    mesh form of Sec. 6): a two-sheet mesh scene of n_pairs broad-phase pairs,
+    gamma from ccd_scene_gamma, then ccd_batch_indexed (gather + root finder)."""
+    from paper_2009_13349_amd import ccd, workloads as W
+    s = W.mesh_scene(n_pairs, seed=5)
+    dev = torch.device("cuda:0")
+    v0, v1 = torch.from_numpy(s["v0"]).to(dev), torch.from_numpy(s["v1"]).to(dev)
+    ids, kind = torch.from_numpy(s["ids"]).to(dev), torch.from_numpy(s["kind"]).to(dev)
+    ctx.set_engine(ccd.ENGINE_PERSISTENT)
+    ctx.enable_timing(False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    g = ctx.scene_gamma(v0, v1)
+    ev[0].record()
+    g = ctx.scene_gamma(v0, v1, out=g)
+    ev[1].record()
+    torch.cuda.synchronize()
+    gamma_ms = ev[0].elapsed_time(ev[1])
+    out = ctx.batch_indexed(v0, v1, ids, kind, gamma=g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.batch_indexed(v0, v1, ids, kind, gamma=g, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"workload": s["name"], "vertices": int(s["v0"].shape[0]), "value": round(n_pairs * steps / t, 1),
+            "ms_per_step": round(1e3 * t / steps, 3), "hits": int(out.hit.sum().item()),
+            "scene_gamma_ms": round(gamma_ms, 4), "gamma": [float(x) for x in g.cpu().numpy()]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +312,7 @@ def main():
                  "ms_per_step": round(1e3 * t_s / args.steps, 3),
                  "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
                  "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
+    indexed = measure_indexed(ctx, torch, args.steps)
     rl = roofline(stats_p, kind_counts)
     tier = KERNELS.index(rl["kernel"]) - 1
     rl["symbol"] = kernel_symbol(tier, ctx.tuning())
@@ -325,6 +356,7 @@ def main():
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,
         "shortened_interval": shortened,
+        "indexed": indexed,
     }
     line["serve"] = (serve_latency(w, torch, value, args.serve_requests)
                      if args.serve_requests > 0 and args.workload == "simulation" else None)

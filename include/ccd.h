@@ -251,6 +251,50 @@ int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
  */
 int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, void* stream);
 
+/*
+ * Candidate pairs over shared vertex arrays (Sec. 6: the active-set and line
+ * search drivers run CCD on the pairs of a mesh's broad phase), with an
+ * optional scene-wide filter.
+ *
+ * Query q is made of vertices ids[4q .. 4q+3] of v0 (positions at t = 0) and
+ * v1 (at t = 1): VF (p, v1, v2, v3), EE (p1, p2, p3, p4).  An id outside
+ * [0, n_vertices) makes the query invalid (status CCD_ST_INVALID).
+ *
+ * gamma: NULL, or 3 doubles, the scene-wide gamma per axis.  Sec. 6 computes
+ * the tolerances of eq. ccd-error / msccd-error from the maximum over all the
+ * vertices of the scene, so that they are the same for every query of a step;
+ * eps_c = K gamma_c^3 then replaces the query's own.  A query whose own gamma
+ * (max(1, max |x^c|) over its 8 points) exceeds gamma_c is invalid, as is one
+ * with min_sep >= min_c gamma_c.  ccd_scene_gamma() computes gamma.
+ *
+ * Device memory only (on_device must be 1), asynchronous on `stream`; the
+ * context's scratch holds the gathered coordinates (24 doubles per query).
+ */
+typedef struct ccd_indexed_desc {
+    int64_t n;                 /* number of queries (candidate pairs), >= 0 */
+    int64_t n_vertices;        /* vertices in v0 / v1 */
+    const double* v0;          /* [n_vertices][3] positions at t = 0 */
+    const double* v1;          /* [n_vertices][3] positions at t = 1 */
+    const int32_t* ids;        /* [n][4] vertex ids per query */
+    const uint8_t* kind;       /* [n] CCD_KIND_*; NULL: every query is default_kind */
+    const double* gamma;       /* [3] scene-wide gamma, or NULL for each query's own */
+    uint8_t default_kind;
+    uint8_t reserved[7];
+    ccd_params params;         /* batch parameters */
+    int32_t on_device;         /* must be 1 */
+    int32_t reserved2;
+} ccd_indexed_desc;
+int ccd_batch_indexed(ccd_context* ctx, const ccd_indexed_desc* d, const ccd_result_soa* out,
+                      void* stream);
+
+/*
+ * Scene-wide gamma per axis: gamma_c = max(1, max over the vertices of v0 and
+ * v1 of |x^c|), non-finite coordinates skipped.  Device pointers; gamma: 3
+ * device doubles, 8-byte aligned.  Asynchronous on `stream`.
+ */
+int ccd_scene_gamma(ccd_context* ctx, const double* v0, const double* v1, int64_t n_vertices,
+                    double* gamma, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /*
  * Serving: continuous batching of requests on one GPU.

@@ -33,7 +33,7 @@
 //   * the m_I test sits where Alg. 2 puts it: inside the colliding branch.
 //   * a split never goes below 2^-52 on an axis: a colliding box whose split axis
 //     is already at depth 52 is treated as terminal, so every endpoint and every
-//     complement 1-t, 1-u, (1-u)-v stays exact.
+//     complement 1-t, 1-u, (1-u)-v stays exact (1-t only while t_max = 1).
 //   * n_checks is reported saturated at m_I.
 //   * shortened time interval (Sec. 6, line search: only the initial I changes):
 //     I_t = [0, t_max], 0 < t_max <= 1, bisected in the normalized coordinate

@@ -27,7 +27,8 @@ EXPORTED = [
     "ccd_context_set_engine", "ccd_context_get_tuning", "ccd_context_set_tuning", "ccd_batch",
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
     "ccd_context_enable_graphs", "ccd_context_graph_counts", "ccd_autotune",
-    "ccd_tuning_cache_store", "ccd_tuning_cache_load", "ccd_min_toi",
+    "ccd_tuning_cache_store", "ccd_tuning_cache_load", "ccd_min_toi", "ccd_batch_indexed",
+    "ccd_scene_gamma",
 ]
 
 
@@ -65,6 +66,14 @@ class BatchDesc(ctypes.Structure):
                 ("default_kind", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 7),
                 ("delta_q", ctypes.c_void_p), ("max_iter_q", ctypes.c_void_p),
                 ("min_sep_q", ctypes.c_void_p), ("params", Params),
+                ("on_device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class IndexedDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_vertices", ctypes.c_int64), ("v0", ctypes.c_void_p),
+                ("v1", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("kind", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p), ("default_kind", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8 * 7), ("params", Params),
                 ("on_device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
@@ -117,6 +126,8 @@ def _lib():
         L.ccd_context_graph_counts.argtypes = [V, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.ccd_context_last_stats.argtypes = [V, P(Stats)]
         L.ccd_min_toi.argtypes = [V, V, ctypes.c_int64, V, V]
+        L.ccd_batch_indexed.argtypes = [V, P(IndexedDesc), P(ResultSoA), V]
+        L.ccd_scene_gamma.argtypes = [V, V, V, ctypes.c_int64, V, V]
         L.ccd_strerror.argtypes = [ctypes.c_int]
         L.ccd_strerror.restype = ctypes.c_char_p
         L.ccd_last_error.argtypes = []
@@ -317,6 +328,71 @@ class Context:
                               ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:
             raise CCDError(rc, "ccd_batch")
+        self._keep = keep
+        return out
+
+    def scene_gamma(self, v0, v1, out=None, stream=None):
+        """Scene-wide gamma per axis of vertex arrays v0, v1 (device float64
+        [nv, 3]) into a 3-element device tensor, asynchronously."""
+        import torch
+        assert v0.is_cuda and v0.dtype == torch.float64 and v0.shape == v1.shape
+        v0, v1 = v0.contiguous(), v1.contiguous()
+        if out is None:
+            out = torch.empty(3, dtype=torch.float64, device=v0.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(v0.device)
+        rc = _lib().ccd_scene_gamma(self._h, ctypes.c_void_p(v0.data_ptr()),
+                                    ctypes.c_void_p(v1.data_ptr()), v0.shape[0],
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise CCDError(rc, "ccd_scene_gamma")
+        self._keep_gamma = (v0, v1, out)
+        return out
+
+    def batch_indexed(self, v0, v1, ids, kind=None, default_kind=0, gamma=None, delta=1e-6,
+                      max_iter=1_000_000, min_sep=0.0, literal=False, t_max=1.0,
+                      out: BatchResult | None = None, stream=None) -> BatchResult:
+        """Asynchronous batch of candidate pairs over shared vertex arrays (device
+        tensors): v0, v1 float64 [nv, 3]; ids int32 [n, 4]; kind uint8 [n];
+        gamma: float64 [3] scene-wide gamma or None."""
+        import torch
+        assert v0.is_cuda and v0.dtype == torch.float64 and v0.shape == v1.shape and v0.shape[-1] == 3
+        assert ids.is_cuda and ids.dtype == torch.int32 and ids.dim() == 2 and ids.shape[1] == 4
+        v0, v1, ids = v0.contiguous(), v1.contiguous(), ids.contiguous()
+        n = ids.shape[0]
+        dev = ids.device
+        if out is None:
+            out = BatchResult(
+                toi=torch.empty(n, dtype=torch.float64, device=dev),
+                t_width=torch.empty(n, dtype=torch.float64, device=dev),
+                hit=torch.empty(n, dtype=torch.uint8, device=dev),
+                n_checks=torch.empty(n, dtype=torch.int64, device=dev),
+                status=torch.empty(n, dtype=torch.uint8, device=dev))
+        keep = [v0, v1, ids]
+        d = IndexedDesc()
+        d.n, d.n_vertices = n, v0.shape[0]
+        d.v0, d.v1, d.ids = v0.data_ptr(), v1.data_ptr(), ids.data_ptr()
+        if kind is not None:
+            kind = kind.contiguous()
+            assert kind.dtype == torch.uint8 and kind.is_cuda and kind.numel() == n
+            keep.append(kind)
+            d.kind = kind.data_ptr()
+        if gamma is not None:
+            gamma = gamma.contiguous()
+            assert gamma.dtype == torch.float64 and gamma.is_cuda and gamma.numel() == 3
+            keep.append(gamma)
+            d.gamma = gamma.data_ptr()
+        d.default_kind = default_kind
+        d.params = params(delta, max_iter, min_sep, literal, t_max)
+        d.on_device = 1
+        o = ResultSoA(out.toi.data_ptr(), out.t_width.data_ptr(), out.hit.data_ptr(),
+                      out.n_checks.data_ptr(), out.status.data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = _lib().ccd_batch_indexed(self._h, ctypes.byref(d), ctypes.byref(o),
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise CCDError(rc, "ccd_batch_indexed")
         self._keep = keep
         return out
 

@@ -7,9 +7,11 @@
 //   p(t)  = (1-t) p0 + t p1                                 (Sec. 3)
 //   F_ee  = ((1-u) p1 + u p2) - ((1-v) p3 + v p4)          (Sec. 3, eq. F-ee)
 //   F_vf  = p - (((1-u-v) v1 + u v2) + v v3)                (Sec. 3, eq. F-vf)
-// with the complements 1-t, 1-u and (1-u)-v exact (box endpoints are dyadic
-// with at most 52 fractional bits), which keeps the rounding error of F below
-// the static filter of Sec. 4.2.
+// The complements 1-u and (1-u)-v are exact (u, v endpoints are dyadic with at
+// most 52 fractional bits), and so is 1-t on the full time interval; on a
+// shortened interval [0, t_max] the time values fl(t_max s) are not dyadic and
+// 1-t is rounded once, which the static filter of Sec. 4.2 (derived for any
+// inputs in [0,1]) still covers.
 //
 // Boxes are integer dyadic triples: on a level with per-axis bisection depths
 // (dt, du, dv) the box (it, iu, iv) is
@@ -208,6 +210,30 @@ __device__ __forceinline__ bool vf_admit(uint64_t iu, int du, uint64_t iv, int d
     const uint64_t a = iu << (D - du);
     const uint64_t b = iv << (D - dv);
     return a + b <= (1ull << D);
+}
+
+// Scene-wide filter (Sec. 6: tolerances from the maximum over all the vertices
+// of the scene): eps_c = K gamma_c^3 with the given gamma, valid for a query
+// only if gamma_c is at least the query's own gamma_c (then the filter's bound
+// covers it).  Returns false otherwise; gamma_min as filter_eps().
+__device__ __forceinline__ bool filter_eps_scene(int kind, const double* X, double min_sep,
+                                                 const double* gamma, double eps[3],
+                                                 double* gamma_min) {
+    const double K = filter_constant(kind, min_sep);
+    bool ok = true;
+    double gmin = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double g = 1.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g = fmax(g, fabs(X[3 * k + c]));
+        const double s = gamma[c];
+        ok = ok && (s >= g) && (s <= 1.7976931348623157e308);  // false for NaN
+        eps[c] = ((K * s) * s) * s;
+        gmin = (c == 0) ? s : fmin(gmin, s);
+    }
+    *gamma_min = gmin;
+    return ok;
 }
 
 // Validation of a query (coordinates finite and bounded, parameters in range).

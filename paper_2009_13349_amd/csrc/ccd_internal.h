@@ -64,6 +64,7 @@ struct BatchArgs {
     const int64_t* order;          // [n] query order grouped by kind, or null (identity)
     const ReqEntry* reqs;          // serving: request table, or null
     int64_t nreq;
+    const double* gamma;           // scene-wide gamma per axis [3], or null (per query)
 };
 
 // A query handed from one engine to the next, at the start of a level.  The

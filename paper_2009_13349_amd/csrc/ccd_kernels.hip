@@ -142,8 +142,11 @@ __device__ __forceinline__ void load_query(const BatchArgs& a, int64_t v, Query&
     Q.literal = (w.flags & kFlagLiteral) != 0;
     Q.tmax = w.t_max;
     double gmin;
-    filter_eps(Q.kind, Q.X, Q.min_sep, Q.eps, &gmin);
-    valid = (Q.kind == kVF || Q.kind == kEE) && query_valid(Q.X, Q.delta, Q.max_iter, Q.min_sep, gmin);
+    bool gok = true;
+    if (a.gamma) gok = filter_eps_scene(Q.kind, Q.X, Q.min_sep, a.gamma, Q.eps, &gmin);
+    else filter_eps(Q.kind, Q.X, Q.min_sep, Q.eps, &gmin);
+    valid = gok && (Q.kind == kVF || Q.kind == kEE) &&
+            query_valid(Q.X, Q.delta, Q.max_iter, Q.min_sep, gmin);
 }
 
 // The split rule compares w(I_t) kappa_t with w(I_t) = tmax * 2^-dt (exact).
@@ -526,6 +529,61 @@ __global__ __launch_bounds__(1024) void k_root(BatchArgs a, int64_t* order) {
     const uint64_t lt = lanemask_lt();
     if (vf) order[base[0] + ov + __popcll(mv & lt)] = q;
     if (ee) order[a.n - 1 - (int64_t)(base[1] + oe + __popcll(me & lt))] = q;
+}
+
+// Candidate pairs given as vertex ids over shared vertex arrays (the active-set
+// and line-search drivers of Sec. 6 work on a mesh): the 8 points of query q
+// are gathered into the structure-of-arrays layout pos[(3k+c)*n + q].  An id
+// outside [0, nv) gives the query NaN coordinates, which makes it invalid.
+__global__ void k_gather(int64_t n, const double* v0, const double* v1, const int32_t* ids,
+                         int64_t nv, double* pos) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t id = ids[4 * q + k];
+        const bool ok = id >= 0 && id < nv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pos[(int64_t)(3 * k + c) * n + q] = ok ? v0[3 * id + c] : nan;
+            pos[(int64_t)(3 * (k + 4) + c) * n + q] = ok ? v1[3 * id + c] : nan;
+        }
+    }
+}
+
+// Scene-wide gamma per axis: max(1, max over the vertices at t = 0 and t = 1 of
+// |x^c|), non-finite coordinates skipped (their queries are invalid anyway).
+// Non-negative doubles order like their bit patterns: integer atomic max.
+__global__ void k_scene_gamma_init(unsigned long long* g) {
+    if (threadIdx.x < 3) g[threadIdx.x] = (unsigned long long)__double_as_longlong(1.0);
+}
+
+__global__ __launch_bounds__(256) void k_scene_gamma(const double* v0, const double* v1,
+                                                     int64_t nv, unsigned long long* g) {
+    double m[3] = {1.0, 1.0, 1.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += stride) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double a = fabs(v0[3 * i + c]), b = fabs(v1[3 * i + c]);
+            if (a <= 1.7976931348623157e308) m[c] = fmax(m[c], a);
+            if (b <= 1.7976931348623157e308) m[c] = fmax(m[c], b);
+        }
+    }
+    __shared__ double wm[4][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m[c] = fmax(m[c], __shfl_xor(m[c], off));
+        if (__lane_id() == 0) wm[threadIdx.x >> 6][c] = m[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const double r = fmax(fmax(wm[0][c], wm[1][c]), fmax(wm[2][c], wm[3][c]));
+        atomicMax(&g[c], (unsigned long long)__double_as_longlong(r));
+    }
 }
 
 // Smallest toi of a batch: the line search bounds its step by the earliest time
@@ -1587,6 +1645,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
             const double K = filter_constant(kind, min_sep);
             double gm = 1.0;
             for (int k = 0; k < 8; ++k) gm = fmax(gm, fabs(sh.Xs[tid * 8 + k]));
+            if (a.gamma) gm = a.gamma[tid];  // scene-wide filter (checked at level 0)
             sh.Es[tid] = ((K * gm) * gm) * gm;
         }
         double kappa[3];

@@ -30,6 +30,10 @@ template <int W, int OCC>
 __global__ void k_group(BatchArgs a, GroupCfg g);
 __global__ void k_root(BatchArgs a, int64_t* order);
 __global__ void k_min_toi_init(unsigned long long* out);
+__global__ void k_gather(int64_t n, const double* v0, const double* v1, const int32_t* ids,
+                         int64_t nv, double* pos);
+__global__ void k_scene_gamma_init(unsigned long long* g);
+__global__ void k_scene_gamma(const double* v0, const double* v1, int64_t nv, unsigned long long* g);
 __global__ void k_min_toi(const double* toi, int64_t n, unsigned long long* out);
 __global__ void k_reset(unsigned long long* counters);
 }  // namespace ccd
@@ -82,7 +86,8 @@ struct ccd_context {
     int engine = CCD_ENGINE_PERSISTENT;
     ccd_tuning tune{};
     DevBuf counters, order, lane_arena, rec_a, group_arena, rec_b, block_arena;
-    DevBuf io;  // staging for host-pointer batches
+    DevBuf io;      // staging for host-pointer batches
+    DevBuf gather;  // structure-of-arrays coordinates of an indexed batch
     bool timing = false;
     hipEvent_t ev[5] = {};
     bool have_events = false;
@@ -505,7 +510,7 @@ void ccd_context_destroy(ccd_context* c) {
     (void)set_device(c->device);
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&c->counters, &c->order, &c->lane_arena, &c->rec_a, &c->group_arena,
-                      &c->rec_b, &c->block_arena, &c->io})
+                      &c->rec_b, &c->block_arena, &c->io, &c->gather})
         release(*b);
     if (c->have_events)
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
@@ -907,6 +912,72 @@ int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, voi
     }
     if (!record_hip(hipGetLastError(), "ccd_min_toi launch")) return CCD_EDEVICE;
     return CCD_OK;
+}
+
+int ccd_scene_gamma(ccd_context* ctx, const double* v0, const double* v1, int64_t n_vertices,
+                    double* gamma, void* stream) {
+    if (!ctx || n_vertices < 0 || !gamma || (n_vertices > 0 && (!v0 || !v1))) {
+        set_last_error("ccd_scene_gamma: null pointer or negative count");
+        return CCD_EINVAL;
+    }
+    if (((uintptr_t)gamma & 7) != 0) {
+        set_last_error("ccd_scene_gamma: gamma is not 8-byte aligned");
+        return CCD_EINVAL;
+    }
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* g = reinterpret_cast<unsigned long long*>(gamma);
+    hipLaunchKernelGGL(k_scene_gamma_init, dim3(1), dim3(64), 0, s, g);
+    if (n_vertices > 0) {
+        const int64_t blocks = std::min<int64_t>((n_vertices + 255) / 256, (int64_t)ctx->num_cu * 2);
+        hipLaunchKernelGGL(k_scene_gamma, dim3((unsigned)blocks), dim3(256), 0, s, v0, v1,
+                           n_vertices, g);
+    }
+    if (!record_hip(hipGetLastError(), "ccd_scene_gamma launch")) return CCD_EDEVICE;
+    return CCD_OK;
+}
+
+int ccd_batch_indexed(ccd_context* ctx, const ccd_indexed_desc* d, const ccd_result_soa* out,
+                      void* stream) {
+    if (!ctx || !d || !out) return CCD_EINVAL;
+    if (d->n < 0 || d->n_vertices < 0 || !params_ok(d->params) || d->default_kind > 1)
+        return CCD_EINVAL;
+    if (!d->on_device) {
+        set_last_error("ccd_batch_indexed: inputs and outputs must be device memory");
+        return CCD_EINVAL;
+    }
+    if (d->params.max_iter < 1) return CCD_EINVAL;
+    if (d->n == 0) return CCD_OK;
+    if (!d->ids || (d->n_vertices > 0 && (!d->v0 || !d->v1)) || !out->toi || !out->t_width ||
+        !out->hit || !out->n_checks || !out->status)
+        return CCD_EINVAL;
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = d->n;
+    if ((size_t)24 * n * 8 > ctx->budget) return CCD_ENOMEM;
+    if (!grow(ctx->gather, (size_t)24 * n * 8)) return CCD_ENOMEM;
+    double* pos = (double*)ctx->gather.p;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d->v0,
+                       d->v1, d->ids, d->n_vertices, pos);
+    if (!record_hip(hipGetLastError(), "ccd_batch_indexed gather")) return CCD_EDEVICE;
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.pos = pos;
+    a.kind = d->kind;
+    a.default_kind = d->default_kind;
+    a.delta = d->params.delta;
+    a.max_iter = d->params.max_iter;
+    a.min_sep = d->params.min_sep;
+    a.t_max = d->params.t_max;
+    a.flags = d->params.flags;
+    a.gamma = d->gamma;
+    a.toi = out->toi;
+    a.t_width = out->t_width;
+    a.hit = out->hit;
+    a.n_checks = out->n_checks;
+    a.status = out->status;
+    return ccd::run_args(ctx, a, d->params.max_iter, s);
 }
 
 int ccd_vf(const double x0[4][3], const double x1[4][3], const ccd_params* p, ccd_result* out) {

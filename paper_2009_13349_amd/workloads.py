@@ -534,3 +534,76 @@ def concat(ws) -> dict:
     out["kind"] = np.concatenate([w["kind"] for w in ws])
     out["cls"] = np.concatenate([w["cls"] for w in ws])
     return out
+
+
+# ---------------------------------------------------------------------------
+# Candidate pairs over shared vertex arrays (the mesh form the active-set and
+# line-search drivers of Sec. 6 work on).
+
+def as_indexed(w: dict) -> dict:
+    """The queries of a structure-of-arrays workload as vertex arrays and ids:
+    query q's 4 points become vertices 4q..4q+3 (no sharing), so an indexed
+    batch must reproduce the workload's results exactly."""
+    n = w["pos"].shape[1]
+    P = w["pos"].T.reshape(n, 8, 3)
+    v0 = np.ascontiguousarray(P[:, :4, :].reshape(4 * n, 3))
+    v1 = np.ascontiguousarray(P[:, 4:, :].reshape(4 * n, 3))
+    ids = np.arange(4 * n, dtype=np.int32).reshape(n, 4)
+    return {"v0": v0, "v1": v1, "ids": ids, "kind": w["kind"].copy(), "name": w.get("name", "") + "_indexed",
+            "delta": w.get("delta", 1e-6), "max_iter": w.get("max_iter", 1_000_000),
+            "min_sep": w.get("min_sep", 0.0)}
+
+
+def gather(scene: dict) -> np.ndarray:
+    """Structure-of-arrays positions pos[24, n] of an indexed scene."""
+    ids = scene["ids"]
+    P = np.concatenate([scene["v0"][ids], scene["v1"][ids]], axis=1)  # [n, 8, 3]
+    return np.ascontiguousarray(P.reshape(ids.shape[0], 24).T)
+
+
+def mesh_scene(n_pairs: int = 100_000, seed: int = 5, h: float = 2e-3, vf_frac: float = 0.6) -> dict:
+    """Two triangulated g x g sheets on [0,1]^2: sheet A static at z = 0, sheet B
+    (offset by half a cell) moving from z = +h to z = -h through A, with small
+    in-plane jitter.  Candidate pairs as a broad phase would give them: VF =
+    (vertex of B, triangle of A under it), EE = (edge of B, edge of A in the
+    same cell).  Vertices are shared by many pairs."""
+    rng = _rng(seed)
+    g = max(4, int(math.ceil(math.sqrt(n_pairs / 4.0))) + 2)
+    cell = 1.0 / (g - 1)
+    ii, jj = np.meshgrid(np.arange(g), np.arange(g), indexing="ij")
+    base = np.stack([ii.ravel() * cell, jj.ravel() * cell], axis=1)
+    A0 = np.concatenate([base + rng.uniform(-0.1, 0.1, base.shape) * cell, np.zeros((g * g, 1))], axis=1)
+    A1 = A0.copy()
+    B0 = np.concatenate([base + 0.5 * cell + rng.uniform(-0.1, 0.1, base.shape) * cell,
+                         np.full((g * g, 1), h)], axis=1)
+    B1 = B0 + np.concatenate([rng.normal(0, 0.02, (g * g, 2)) * cell,
+                              -2 * h * np.ones((g * g, 1)) + rng.normal(0, 0.1 * h, (g * g, 1))], axis=1)
+    v0 = np.ascontiguousarray(np.concatenate([A0, B0]))
+    v1 = np.ascontiguousarray(np.concatenate([A1, B1]))
+    nA = g * g
+    idx = lambda i, j: i * g + j  # noqa: E731
+    n_vf = int(round(n_pairs * vf_frac))
+    n_ee = n_pairs - n_vf
+    # VF: vertex (i, j) of B lies over cell (i, j) of A, whose two triangles are tried
+    ci = rng.integers(0, g - 1, n_vf)
+    cj = rng.integers(0, g - 1, n_vf)
+    upper = rng.integers(0, 2, n_vf).astype(bool)
+    a00, a10, a01, a11 = idx(ci, cj), idx(ci + 1, cj), idx(ci, cj + 1), idx(ci + 1, cj + 1)
+    tri = np.where(upper[:, None], np.stack([a10, a11, a01], 1), np.stack([a00, a10, a01], 1))
+    vf = np.concatenate([(nA + idx(ci, cj))[:, None], tri], axis=1)
+    # EE: an edge of B's cell against an edge of A's cell
+    ci = rng.integers(0, g - 1, n_ee)
+    cj = rng.integers(0, g - 1, n_ee)
+
+    def cell_edge(off, i, j, which):
+        e0 = np.where(which == 0, idx(i, j), np.where(which == 1, idx(i, j), idx(i + 1, j)))
+        e1 = np.where(which == 0, idx(i + 1, j), np.where(which == 1, idx(i, j + 1), idx(i, j + 1)))
+        return off + e0, off + e1
+
+    ea0, ea1 = cell_edge(0, ci, cj, rng.integers(0, 3, n_ee))
+    eb0, eb1 = cell_edge(nA, ci, cj, rng.integers(0, 3, n_ee))
+    ee = np.stack([eb0, eb1, ea0, ea1], axis=1)
+    ids = np.ascontiguousarray(np.concatenate([vf, ee]).astype(np.int32))
+    kind = np.concatenate([np.full(n_vf, VF, np.uint8), np.full(n_ee, EE, np.uint8)])
+    return {"v0": v0, "v1": v1, "ids": ids, "kind": kind, "name": f"mesh_scene_{n_pairs}",
+            "delta": 1e-6, "max_iter": 1_000_000, "min_sep": 0.0}

@@ -60,14 +60,33 @@ def test_host_only_entry_points(lib):
     assert (p.delta, p.max_iter, p.min_sep, p.t_max, p.flags) == (1e-6, 1_000_000, 0.0, 1.0, 0)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the size and field offsets of the C structs: a C
+    program compiled against include/ccd.h prints them."""
     from paper_2009_13349_amd import ccd
-    assert ctypes.sizeof(ccd.Params) == 40
-    assert ctypes.sizeof(ccd.Result) == 32
-    assert ctypes.sizeof(ccd.Tuning) == 40
-    assert ctypes.sizeof(ccd.BatchDesc) == 104
-    assert ctypes.sizeof(ccd.ResultSoA) == 40
-    assert ctypes.sizeof(ccd.Stats) == 104
+    mirrors = {"ccd_params": ccd.Params, "ccd_result": ccd.Result, "ccd_tuning": ccd.Tuning,
+               "ccd_batch_desc": ccd.BatchDesc, "ccd_result_soa": ccd.ResultSoA,
+               "ccd_stats": ccd.Stats, "ccd_indexed_desc": ccd.IndexedDesc,
+               "ccd_serve_config": ccd.ServeConfig, "ccd_serve_info": ccd.ServeInfo,
+               "ccd_serve_stats": ccd.ServeStats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ccd.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+    assert ctypes.sizeof(ccd.IndexedDesc) == 112 and ctypes.sizeof(ccd.BatchDesc) == 104
 
 
 def test_null_arguments_rejected_without_gpu(lib):

@@ -1,0 +1,137 @@
+"""GPU <-> oracle parity of candidate pairs over shared vertex arrays and of
+the scene-wide filter (Sec. 6), called through the C ABI.  Bar: every output
+bit-identical."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_13349_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("toi", "t_width", "hit", "n_checks", "status")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ccdmod():
+    from paper_2009_13349_amd import ccd
+    ccd.load()
+    return ccd
+
+
+@pytest.fixture()
+def ctx(ccdmod, torch_dev):
+    c = ccdmod.Context(0)
+    yield c
+    c.close()
+
+
+def to_np(r):
+    out = {k: getattr(r, k).cpu().numpy() for k in FIELDS}
+    out["n_checks"] = out["n_checks"].astype(np.uint64)
+    return out
+
+
+def assert_same(got, ref, what):
+    for k in FIELDS:
+        if k in ("toi", "t_width"):
+            g = np.ascontiguousarray(got[k], dtype=np.float64).view(np.int64)
+            r = np.ascontiguousarray(ref[k], dtype=np.float64).view(np.int64)
+        else:
+            g, r = np.asarray(got[k]).astype(np.int64), np.asarray(ref[k]).astype(np.int64)
+        bad = np.nonzero(g != r)[0]
+        assert len(bad) == 0, (f"{what}: {k} differs at {len(bad)} queries, first {bad[:5].tolist()}: "
+                               f"gpu {np.asarray(got[k])[bad[:5]]} oracle {np.asarray(ref[k])[bad[:5]]}")
+
+
+def dev_scene(torch, dev, s):
+    return (torch.from_numpy(s["v0"]).to(dev), torch.from_numpy(s["v1"]).to(dev),
+            torch.from_numpy(s["ids"]).to(dev), torch.from_numpy(s["kind"]).to(dev))
+
+
+def test_indexed_reproduces_structure_of_arrays(ctx, torch_dev):
+    torch, dev = torch_dev
+    w = W.concat([W.uniform_vf(2000, seed=81), W.edge_edge_mixed(2000, seed=82),
+                  W.subset(W.simulation_mixed(20_000, seed=83), np.arange(0, 20_000, 4))])
+    s = W.as_indexed(w)
+    v0, v1, ids, kind = dev_scene(torch, dev, s)
+    ref = oracle.solve_batch(w["pos"], w["kind"], max_iter=200_000)
+    for engine in (0, 1):
+        ctx.set_engine(engine)
+        got = to_np(ctx.batch_indexed(v0, v1, ids, kind, max_iter=200_000))
+        torch.cuda.synchronize()
+        assert_same(got, ref, f"indexed engine {engine}")
+        soa = to_np(ctx.batch_device(torch.from_numpy(w["pos"]).to(dev), kind, max_iter=200_000))
+        assert_same(soa, ref, f"structure of arrays engine {engine}")
+
+
+def test_scene_gamma_matches_numpy(ctx, torch_dev):
+    torch, dev = torch_dev
+    s = W.mesh_scene(30_000, seed=84)
+    v0 = s["v0"].copy()
+    v1 = s["v1"].copy()
+    v0[5] = [-7.5, 0.25, 3.0]
+    v1[9] = [0.5, np.nan, np.inf]  # non-finite values are skipped
+    expect = np.maximum(1.0, np.nanmax(np.where(np.isfinite(np.concatenate([v0, v1])),
+                                                np.abs(np.concatenate([v0, v1])), np.nan), axis=0))
+    got = ctx.scene_gamma(torch.from_numpy(v0).to(dev), torch.from_numpy(v1).to(dev))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), expect)
+    # an empty scene: the floor
+    e = torch.zeros((0, 3), dtype=torch.float64, device=dev)
+    assert np.array_equal(ctx.scene_gamma(e, e).cpu().numpy(), np.ones(3))
+
+
+@pytest.mark.parametrize("scale,t_max", [(1.0, 1.0), (4.0, 1.0), (1.0, 0.5), (3.5, 0.25)])
+def test_mesh_scene_parity(ctx, torch_dev, scale, t_max):
+    """Shared vertices, a scene gamma (the scene's own, or a wider one) and a
+    shortened interval, through both engines and the forced group engines."""
+    torch, dev = torch_dev
+    s = W.mesh_scene(40_000, seed=85)
+    v0, v1, ids, kind = dev_scene(torch, dev, s)
+    g = ctx.scene_gamma(v0, v1) * scale
+    torch.cuda.synchronize()
+    ref = oracle.solve_batch(W.gather(s), s["kind"], max_iter=100_000, t_max=t_max,
+                             gamma=g.cpu().numpy())
+    assert ref["invalid"] == 0
+    for engine, tune in ((0, {}), (1, {}), (0, {"lane_capacity": 8, "lane_budget": 1})):
+        if tune:
+            ctx.set_tuning(**tune)
+        ctx.set_engine(engine)
+        got = to_np(ctx.batch_indexed(v0, v1, ids, kind, gamma=g, max_iter=100_000, t_max=t_max))
+        assert_same(got, ref, f"mesh scale {scale} t_max {t_max} engine {engine} tuning {tune}")
+
+
+def test_invalid_ids_and_too_small_gamma(ccdmod, ctx, torch_dev):
+    torch, dev = torch_dev
+    s = W.mesh_scene(5_000, seed=86)
+    s["ids"] = s["ids"].copy()
+    s["ids"][7, 2] = -1
+    s["ids"][11, 0] = s["v0"].shape[0]  # one past the end
+    v0, v1, ids, kind = dev_scene(torch, dev, s)
+    got = to_np(ctx.batch_indexed(v0, v1, ids, kind, max_iter=100_000))
+    assert got["status"][7] == ccdmod.ST_INVALID and got["status"][11] == ccdmod.ST_INVALID
+    assert np.isnan(got["toi"][7]) and np.isnan(got["toi"][11])
+    ok = np.ones(len(s["kind"]), bool)
+    ok[[7, 11]] = False
+    assert np.all(got["status"][ok] != ccdmod.ST_INVALID)
+    # a gamma below some queries' own: exactly those are invalid, as in the oracle
+    good = W.mesh_scene(5_000, seed=86)
+    v0, v1, ids, kind = dev_scene(torch, dev, good)
+    g = np.array([1.0, 1.0, 1.0])
+    ref = oracle.solve_batch(W.gather(good), good["kind"], max_iter=100_000, gamma=g)
+    assert 0 < ref["invalid"] < len(good["kind"])
+    got = to_np(ctx.batch_indexed(v0, v1, ids, kind, gamma=torch.from_numpy(g).to(dev),
+                                  max_iter=100_000))
+    ref_status = np.where(ref["status"] == 0xFF, ccdmod.ST_INVALID, ref["status"])
+    assert np.array_equal(got["status"], ref_status)
+    fine = ref["status"] != 0xFF
+    assert np.array_equal(got["toi"][fine].view(np.int64), ref["toi"][fine].view(np.int64))
