@@ -188,6 +188,27 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 32, loa
             "latency": "scheduled arrival -> results in the caller's host arrays"}
 
 
+def measure_extras(ctx, torch, pos, kind, w, n, steps):
+    """The line search's shortened interval (Sec. 6): the same queries over t in
+    [0, 0.5], then the batch-wide smallest toi (the step bound); and the indexed
+    form with a scene-wide filter."""
+    from paper_2009_13349_amd import ccd
+    t_s, _, out_s = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, steps, 1,
+                               timing=False, t_max=0.5)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mt = ctx.min_toi(out_s.toi)
+    ev0.record()
+    for _ in range(10):
+        mt = ctx.min_toi(out_s.toi, out=mt)
+    ev1.record()
+    torch.cuda.synchronize()
+    shortened = {"t_max": 0.5, "value": round(n * steps / t_s, 1),
+                 "ms_per_step": round(1e3 * t_s / steps, 3),
+                 "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
+                 "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
+    return shortened, measure_indexed(ctx, torch, steps)
+
+
 def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
     """Candidate pairs over shared vertex arrays with a scene-wide filter (the
     mesh form of Sec. 6): a two-sheet mesh scene of n_pairs broad-phase pairs,
@@ -234,6 +255,9 @@ def main():
         "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the benchmark workload's batches (for profiler runs): no "
+                         "shortened-interval or indexed measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -297,22 +321,9 @@ def main():
         plain = {"value": round(n * args.steps / t_b, 1), "ms_per_step": round(1e3 * t_b / args.steps, 3),
                  "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
                                    for i in range(4)}}
-    # the line search's shortened interval (Sec. 6): same queries over t in
-    # [0, 0.5], then the batch-wide smallest toi (the step bound)
-    t_s, _, out_s = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps, 1,
-                               timing=False, t_max=0.5)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    mt = ctx.min_toi(out_s.toi)
-    ev0.record()
-    for _ in range(10):
-        mt = ctx.min_toi(out_s.toi, out=mt)
-    ev1.record()
-    torch.cuda.synchronize()
-    shortened = {"t_max": 0.5, "value": round(n * args.steps / t_s, 1),
-                 "ms_per_step": round(1e3 * t_s / args.steps, 3),
-                 "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
-                 "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
-    indexed = measure_indexed(ctx, torch, args.steps)
+    shortened = indexed = None
+    if not args.main_only:
+        shortened, indexed = measure_extras(ctx, torch, pos, kind, w, n, args.steps)
     rl = roofline(stats_p, kind_counts)
     tier = KERNELS.index(rl["kernel"]) - 1
     rl["symbol"] = kernel_symbol(tier, ctx.tuning())
