@@ -977,7 +977,10 @@ __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* E
     for (int c = 0; c < 3; ++c) {
         if (__ballot(col0 || col1) == 0) break;
         const double* xs = Xs + c * 8;
-        double lo0 = INFINITY, hi0 = -INFINITY, lo1 = INFINITY, hi1 = -INFINITY;
+        // corner ranges per group: 0 = child 0 only, 1 = the shared face,
+        // 2 = child 1 only (4 corners each); each group starts from its first
+        double glo[3] = {0.0, 0.0, 0.0}, ghi[3] = {0.0, 0.0, 0.0};
+        bool gset[3] = {false, false, false};
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             const double ta = tv[a];
@@ -1005,10 +1008,18 @@ __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* E
                         f = P[0] - (s12 + vv[e] * P[3]);
                     }
                     const int sp = SPLIT == 0 ? a : (SPLIT == 1 ? b : e);
-                    if (sp <= 1) { lo0 = fmin(lo0, f); hi0 = fmax(hi0, f); }
-                    if (sp >= 1) { lo1 = fmin(lo1, f); hi1 = fmax(hi1, f); }
+                    if (!gset[sp]) {
+                        glo[sp] = f;
+                        ghi[sp] = f;
+                        gset[sp] = true;
+                    } else {
+                        glo[sp] = fmin(glo[sp], f);
+                        ghi[sp] = fmax(ghi[sp], f);
+                    }
                 }
         }
+        const double lo0 = fmin(glo[0], glo[1]), hi0 = fmax(ghi[0], ghi[1]);
+        const double lo1 = fmin(glo[1], glo[2]), hi1 = fmax(ghi[1], ghi[2]);
         const double eps = Es[c];
         {
             const double l = lo0 - min_sep, h = hi0 + min_sep;
