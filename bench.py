@@ -95,9 +95,10 @@ def kernel_symbol(tier: int, tuning: dict) -> str:
     return f"ccd::k_group<{gw}, {tuning['group_occupancy'] if gw == 1 else 1}>"
 
 
-def hbm_traffic(symbol: str):
-    """Per-launch HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded
-    under profiles/ for these exact kernel sources, else None."""
+def hbm_record(symbol: str):
+    """Per-launch HBM bytes {fetch_bytes, write_bytes} (FETCH_SIZE, WRITE_SIZE,
+    copy-calibrated) recorded under profiles/ for these exact kernel sources,
+    else None."""
     from paper_2009_13349_amd.rocprof_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
@@ -108,7 +109,24 @@ def hbm_traffic(symbol: str):
     k = rec["kernels"].get(symbol)
     if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
         return None
-    return k["fetch_bytes"] + k["write_bytes"]
+    return k
+
+
+def hbm_traffic(symbol: str):
+    k = hbm_record(symbol)
+    return k["fetch_bytes"] + k["write_bytes"] if k else None
+
+
+def query_streaming(stats, n: int):
+    """The root pass reads every query's 24 coordinates and its kind once:
+    its read rate against the 8 TB/s HBM peak."""
+    ms = float(np.mean([s["kernel_ms"][0] for s in stats]))
+    bytes_in = n * (24 * 8 + 1)
+    gbps = bytes_in / (ms * 1e-3) / 1e9
+    k = hbm_record("ccd::k_root")
+    return {"kernel": "root", "algorithmic_bytes_read": bytes_in, "avg_launch_ms": round(ms, 4),
+            "gbps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / 8000.0, 3),
+            "measured_read_bytes": round(k["fetch_bytes"]) if k else None}
 
 
 def cpu_baseline(w, seconds: float):
@@ -331,6 +349,7 @@ def main():
     rl["traffic"] = round(tb) if tb else None
     rl["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     rl["hbm_gbps"] = round(tb / (rl["avg_launch_ms"] * 1e-3) / 1e9, 1) if tb else None
+    streaming = query_streaming(stats_p, n)
     checks_total = int(sum(sum(c) for c in stats_p[-1]["checks"]))
     alg_flops = alg_checks[0] * FLOP_PER_CHECK[0] + alg_checks[1] * FLOP_PER_CHECK[1]
     path_alg_tflops = alg_flops / (t_p / args.steps) / 1e12
@@ -366,6 +385,7 @@ def main():
         "lane_utilization": [round(sum(stats_p[-1]["checks"][i]) / stats_p[-1]["lane_slots"][i], 3)
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,
+        "query_streaming": streaming,
         "shortened_interval": shortened,
         "indexed": indexed,
     }
