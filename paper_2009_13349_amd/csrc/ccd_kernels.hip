@@ -712,53 +712,64 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
         }
         if (q < 0) continue;
 
-        // ---- one box check
-        const bool root = S.level == 0;
-        uint64_t bt = 0, bu = 0, bv = 0;
-        if (!root) {
-            bt = ar[arena_idx(K, cur, idx, 0)];
-            bu = ar[arena_idx(K, cur, idx, 1)];
-            bv = ar[arena_idx(K, cur, idx, 2)];
-        }
-        // kappa (eq. kappas) comes from the corners of [0,1]^3: the level-0 check
-        // produces it when the time interval is the full one
-        const bool fused = root && Q.tmax == 1.0;
-        if (root && !fused) {
-            if (Q.kind == kEE)
-                (void)box_check<kEE>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
-                                     true, Q.kappa);
-            else
-                (void)box_check<kVF>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
-                                     true, Q.kappa);
-        }
-        const CheckResult R = check_any(Q, L, bt, bu, bv, fused, Q.kappa);
-        if (root) L = level_info(Q.kappa, S.d, Q.tmax);
-        nchk[Q.kind] += 1;
-        if (R.collide) {
-            const bool term = R.small || L.dcap;
-            acc_add(A, bt, bu, bv, term, R.small);
-            if (!term) {
-                uint64_t ch[2][3];
-                bool ok[2];
-                children(Q.kind, S, L, bt, bu, bv, ch, ok);
+        // ---- one box check (lanes whose level still has boxes)
+        if (idx < S.cnt) {
+            const bool root = S.level == 0;
+            uint64_t bt = 0, bu = 0, bv = 0;
+            if (!root) {
+                bt = ar[arena_idx(K, cur, idx, 0)];
+                bu = ar[arena_idx(K, cur, idx, 1)];
+                bv = ar[arena_idx(K, cur, idx, 2)];
+            }
+            // kappa (eq. kappas) comes from the corners of [0,1]^3: the level-0 check
+            // produces it when the time interval is the full one
+            const bool fused = root && Q.tmax == 1.0;
+            if (root && !fused) {
+                if (Q.kind == kEE)
+                    (void)box_check<kEE>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
+                                         true, Q.kappa);
+                else
+                    (void)box_check<kVF>(Q.X, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, Q.eps, Q.min_sep, Q.delta,
+                                         true, Q.kappa);
+            }
+            const CheckResult R = check_any(Q, L, bt, bu, bv, fused, Q.kappa);
+            if (root) L = level_info(Q.kappa, S.d, Q.tmax);
+            nchk[Q.kind] += 1;
+            if (R.collide) {
+                const bool term = R.small || L.dcap;
+                acc_add(A, bt, bu, bv, term, R.small);
+                if (!term) {
+                    uint64_t ch[2][3];
+                    bool ok[2];
+                    children(Q.kind, S, L, bt, bu, bv, ch, ok);
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    if (!ok[b]) continue;
-                    if (next_cnt < (uint32_t)K) {
-                        ar[arena_idx(K, cur ^ 1, next_cnt, 0)] = ch[b][0];
-                        ar[arena_idx(K, cur ^ 1, next_cnt, 1)] = ch[b][1];
-                        ar[arena_idx(K, cur ^ 1, next_cnt, 2)] = ch[b][2];
+                    for (int b = 0; b < 2; ++b) {
+                        if (!ok[b]) continue;
+                        if (next_cnt < (uint32_t)K) {
+                            ar[arena_idx(K, cur ^ 1, next_cnt, 0)] = ch[b][0];
+                            ar[arena_idx(K, cur ^ 1, next_cnt, 1)] = ch[b][1];
+                            ar[arena_idx(K, cur ^ 1, next_cnt, 2)] = ch[b][2];
+                        }
+                        next_cnt += 1;
                     }
-                    next_cnt += 1;
                 }
             }
+            idx += 1;
         }
-        idx += 1;
-        if (idx < S.cnt) continue;
+        // ---- end of a level: a lane whose level is checked waits until a quarter
+        // of the wave's busy lanes do, and they run the level-end code together
+        // (the wave then executes it once for all of them instead of at nearly
+        // every step); the decisions themselves are per query, so this changes
+        // only when a lane spends its idle steps
+        {
+            const uint64_t m_end = __ballot(idx >= S.cnt);
+            const uint64_t m_act = __ballot(true);
+            if (__popcll(m_end) * 4 < __popcll(m_act) || idx < S.cnt) continue;
+        }
 
         // ---- end of the level: replay Alg. 2's decisions
         uint64_t rf = 0, rm = 0;
-        if (!root && need_rank(A, S, Q.literal, Q.max_iter, L)) {
+        if (S.level != 0 && need_rank(A, S, Q.literal, Q.max_iter, L)) {
             for (uint32_t i = 0; i < S.cnt; ++i) {
                 const uint64_t kt = ar[arena_idx(K, cur, i, 0)];
                 const uint64_t ku = ar[arena_idx(K, cur, i, 1)];
