@@ -459,7 +459,7 @@ __device__ __forceinline__ void acc_uniform(Acc& A) {
 // ones from the back (counts in kCntOrderFront / kCntOrderBack), so that its
 // wavefronts mostly run one corner formula; the lane engine checks their root
 // box again (it needs the level-0 corners for kappa) and counts that check.
-__global__ __launch_bounds__(1024) void k_root(BatchArgs a, int64_t* order) {
+__global__ __launch_bounds__(512) void k_root(BatchArgs a, int64_t* order) {
     __shared__ unsigned int cnt[2];
     __shared__ unsigned long long base[2];
     __shared__ unsigned int fin[2];

@@ -230,7 +230,7 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
     if (persistent) {
         // level 0 of every query; the survivors, grouped by kind, go on
-        hipLaunchKernelGGL(k_root, dim3((unsigned)((P.n + 1023) / 1024)), dim3(1024), 0, s, a,
+        hipLaunchKernelGGL(k_root, dim3((unsigned)((P.n + 511) / 512)), dim3(512), 0, s, a,
                            (int64_t*)ctx->order.p);
         a.order = (const int64_t*)ctx->order.p;
     }
