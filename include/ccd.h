@@ -268,7 +268,9 @@ int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, voi
  * with min_sep >= min_c gamma_c.  ccd_scene_gamma() computes gamma.
  *
  * Device memory only (on_device must be 1), asynchronous on `stream`; the
- * context's scratch holds the gathered coordinates (24 doubles per query).
+ * context's scratch holds the gathered coordinates (24 doubles per query) and
+ * is reused by the next call: as for ccd_batch, calls on one context must not
+ * overlap on different streams.
  */
 typedef struct ccd_indexed_desc {
     int64_t n;                 /* number of queries (candidate pairs), >= 0 */

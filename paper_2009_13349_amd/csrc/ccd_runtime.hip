@@ -939,18 +939,25 @@ int ccd_scene_gamma(ccd_context* ctx, const double* v0, const double* v1, int64_
 
 int ccd_batch_indexed(ccd_context* ctx, const ccd_indexed_desc* d, const ccd_result_soa* out,
                       void* stream) {
-    if (!ctx || !d || !out) return CCD_EINVAL;
-    if (d->n < 0 || d->n_vertices < 0 || !params_ok(d->params) || d->default_kind > 1)
+    if (!ctx || !d || !out) {
+        set_last_error("ccd_batch_indexed: null context, descriptor or outputs");
         return CCD_EINVAL;
+    }
+    if (d->n < 0 || d->n_vertices < 0 || !params_ok(d->params) || d->default_kind > 1 ||
+        d->params.max_iter < 1) {
+        set_last_error("ccd_batch_indexed: negative count, bad parameters or kind");
+        return CCD_EINVAL;
+    }
     if (!d->on_device) {
         set_last_error("ccd_batch_indexed: inputs and outputs must be device memory");
         return CCD_EINVAL;
     }
-    if (d->params.max_iter < 1) return CCD_EINVAL;
     if (d->n == 0) return CCD_OK;
     if (!d->ids || (d->n_vertices > 0 && (!d->v0 || !d->v1)) || !out->toi || !out->t_width ||
-        !out->hit || !out->n_checks || !out->status)
+        !out->hit || !out->n_checks || !out->status) {
+        set_last_error("ccd_batch_indexed: null input or output array");
         return CCD_EINVAL;
+    }
     if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = d->n;
