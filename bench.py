@@ -151,7 +151,7 @@ def cpu_baseline(w, seconds: float):
                       f"{n}-query workload, single-threaded C++ oracle, {t_used:.1f} s"}
 
 
-def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 32, load: float = 0.7,
+def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, load: float = 0.7,
                   seed: int = 4):
     """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
     log-uniform in [1e-6, 1e-4]) at `load` x the measured batch throughput,
@@ -271,7 +271,7 @@ def main():
                     help="skip the autotuner (default: tune once per device and workload, cached)")
     ap.add_argument("--tuning-cache", default=os.environ.get(
         "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the benchmark workload's batches (for profiler runs): no "
