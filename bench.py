@@ -152,7 +152,7 @@ def cpu_baseline(w, seconds: float):
 
 
 def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, load: float = 0.7,
-                  seed: int = 4):
+                  seed: int = 4, streams: int = 2):
     """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
     log-uniform in [1e-6, 1e-4]) at `load` x the measured batch throughput,
     submitted to the continuous-batching server; latency = scheduled arrival ->
@@ -174,7 +174,7 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
     lam = load * q_sat / mean_n  # requests per second
     gaps = rng.exponential(1.0 / lam, size=requests)
     deltas = np.exp(rng.uniform(math.log(1e-6), math.log(1e-4), size=requests))
-    srv = ccd.Server(streams=2, pool_bytes=16 << 30, scratch_bytes=12 << 30,
+    srv = ccd.Server(streams=streams, pool_bytes=16 << 30, scratch_bytes=12 << 30,
                      max_queries_per_launch=4_000_000)
     # warm-up: one request of each payload size, not timed
     for n, pos, kind in pay[:4]:
@@ -273,6 +273,8 @@ def main():
         "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--serve-streams", type=int, default=2,
+                    help="compute streams of the serving measurement's server")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the benchmark workload's batches (for profiler runs): no "
                          "shortened-interval or indexed measurement")
@@ -389,7 +391,7 @@ def main():
         "shortened_interval": shortened,
         "indexed": indexed,
     }
-    line["serve"] = (serve_latency(w, torch, value, args.serve_requests)
+    line["serve"] = (serve_latency(w, torch, value, args.serve_requests, streams=args.serve_streams)
                      if args.serve_requests > 0 and args.workload == "simulation" else None)
     line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     print(json.dumps(line), flush=True)
