@@ -591,12 +591,19 @@ int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
 }
 
 int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* out, void* stream) {
-    if (!ctx || !d || !out) return CCD_EINVAL;
-    if (d->n < 0 || !params_ok(d->params)) return CCD_EINVAL;
-    if (d->default_kind > 1) return CCD_EINVAL;
-    if (d->n == 0) return CCD_OK;
-    if (!d->pos || !out->toi || !out->t_width || !out->hit || !out->n_checks || !out->status)
+    if (!ctx || !d || !out) {
+        set_last_error("ccd_batch: null context, descriptor or outputs");
         return CCD_EINVAL;
+    }
+    if (d->n < 0 || !params_ok(d->params) || d->default_kind > 1) {
+        set_last_error("ccd_batch: negative count, bad parameters (t_max, flags) or kind");
+        return CCD_EINVAL;
+    }
+    if (d->n == 0) return CCD_OK;
+    if (!d->pos || !out->toi || !out->t_width || !out->hit || !out->n_checks || !out->status) {
+        set_last_error("ccd_batch: null input or output array");
+        return CCD_EINVAL;
+    }
     if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = d->n;
@@ -604,7 +611,10 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
 
     // batch-level parameter checks that do not depend on the queries
     int64_t mi_max = d->params.max_iter;
-    if (!d->max_iter_q && d->params.max_iter < 1) return CCD_EINVAL;
+    if (!d->max_iter_q && d->params.max_iter < 1) {
+        set_last_error("ccd_batch: max_iter < 1");
+        return CCD_EINVAL;
+    }
 
     BatchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -625,7 +635,12 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
             const double dl = d->delta_q ? d->delta_q[q] : d->params.delta;
             const int64_t mi = d->max_iter_q ? d->max_iter_q[q] : d->params.max_iter;
             const double ms = d->min_sep_q ? d->min_sep_q[q] : d->params.min_sep;
-            if (!host_query_valid(X, kind, dl, mi, ms)) return CCD_EINVAL;
+            if (!host_query_valid(X, kind, dl, mi, ms)) {
+                std::snprintf(g_last_error, sizeof(g_last_error),
+                              "ccd_batch: query %lld is invalid (coordinates, kind, delta, "
+                              "max_iter or min_sep)", (long long)q);
+                return CCD_EINVAL;
+            }
             if (d->max_iter_q) mi_max = std::max(mi_max, mi);
         }
         if (d->max_iter_q) {

@@ -266,6 +266,28 @@ def test_ragged_sizes(ctx, torch_dev, n):
         assert_same(got, ref, what=f"n={n} engine={engine}")
 
 
+def test_empty_batches(ctx, torch_dev):
+    """n = 0 on the device, host and indexed entry points returns without
+    launching anything, and the context stays usable."""
+    torch, dev = torch_dev
+    for engine in (0, 1):
+        ctx.set_engine(engine)
+        r = ctx.batch_device(torch.empty((24, 0), dtype=torch.float64, device=dev),
+                             torch.empty(0, dtype=torch.uint8, device=dev))
+        torch.cuda.synchronize()
+        assert r.toi.numel() == 0 and r.status.numel() == 0
+    rh = ctx.batch_host(np.empty((24, 0)))
+    assert rh.toi.size == 0
+    v = torch.zeros((1, 3), dtype=torch.float64, device=dev)
+    ri = ctx.batch_indexed(v, v, torch.empty((0, 4), dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+    assert ri.toi.numel() == 0
+    w = W.concat([W.uniform_vf(100, seed=21), W.edge_edge_mixed(100, seed=22)])
+    for engine in (0, 1):
+        got = run_gpu(ctx, torch_dev, w, engine, max_iter=100_000)
+        assert_same(got, run_oracle(w, max_iter=100_000), what=f"after empty batches, engine {engine}")
+
+
 def test_invalid_queries_on_device(ctx, torch_dev):
     w = W.uniform_vf(64, seed=15)
     w["pos"] = w["pos"].copy()
