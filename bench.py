@@ -208,8 +208,8 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
 
 def measure_extras(ctx, torch, pos, kind, w, n, steps):
     """The line search's shortened interval (Sec. 6): the same queries over t in
-    [0, 0.5], then the batch-wide smallest toi (the step bound); and the indexed
-    form with a scene-wide filter."""
+    [0, 0.5], then the batch-wide smallest toi (the step bound); the indexed
+    form with a scene-wide filter; and the host-pointer form."""
     from paper_2009_13349_amd import ccd
     t_s, _, out_s = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, steps, 1,
                                timing=False, t_max=0.5)
@@ -224,7 +224,25 @@ def measure_extras(ctx, torch, pos, kind, w, n, steps):
                  "ms_per_step": round(1e3 * t_s / steps, 3),
                  "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
                  "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
-    return shortened, measure_indexed(ctx, torch, steps)
+    return shortened, measure_indexed(ctx, torch, steps), measure_host(ctx, w, n)
+
+
+def measure_host(ctx, w, n, runs: int = 2):
+    """The host-pointer form of ccd_batch on the same queries (numpy arrays in
+    pageable host memory): host validation, copies over PCIe both ways and the
+    root finder, as a caller without device buffers sees it."""
+    from paper_2009_13349_amd import ccd
+    ctx.set_engine(ccd.ENGINE_PERSISTENT)
+    ctx.enable_timing(False)
+    pos = np.ascontiguousarray(w["pos"])
+    kind = np.ascontiguousarray(w["kind"])
+    r = ctx.batch_host(pos, kind, delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        r = ctx.batch_host(pos, kind, delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    t = (time.perf_counter() - t0) / runs
+    return {"value": round(n / t, 1), "ms_per_batch": round(1e3 * t, 3), "hits": int(r.hit.sum()),
+            "note": "host arrays in, host arrays out (validation + PCIe copies included)"}
 
 
 def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
@@ -341,9 +359,9 @@ def main():
         plain = {"value": round(n * args.steps / t_b, 1), "ms_per_step": round(1e3 * t_b / args.steps, 3),
                  "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
                                    for i in range(4)}}
-    shortened = indexed = None
+    shortened = indexed = host = None
     if not args.main_only:
-        shortened, indexed = measure_extras(ctx, torch, pos, kind, w, n, args.steps)
+        shortened, indexed, host = measure_extras(ctx, torch, pos, kind, w, n, args.steps)
     rl = roofline(stats_p, kind_counts)
     tier = KERNELS.index(rl["kernel"]) - 1
     rl["symbol"] = kernel_symbol(tier, ctx.tuning())
@@ -390,6 +408,7 @@ def main():
         "query_streaming": streaming,
         "shortened_interval": shortened,
         "indexed": indexed,
+        "host_pointers": host,
     }
     line["serve"] = (serve_latency(w, torch, value, args.serve_requests, streams=args.serve_streams)
                      if args.serve_requests > 0 and args.workload == "simulation" else None)
