@@ -137,6 +137,15 @@ def test_simulation_sample(ctx, torch_dev, engine):
     assert_same(got, ref, what="simulation_mixed_20000")
 
 
+@pytest.mark.parametrize("seed", [7, 8])
+def test_simulation_other_seeds(ctx, torch_dev, seed):
+    """Other draws of the simulation-shaped generator, every output compared."""
+    w = W.simulation_mixed(20000, seed=seed)
+    got = run_gpu(ctx, torch_dev, w, 0)
+    ref = run_oracle(w)
+    assert_same(got, ref, what=f"simulation_mixed_20000 seed {seed}")
+
+
 @pytest.mark.parametrize("d_min,delta", [(1e-4, 1e-6), (1e-3, 1e-4), (1e-4, 1e-4), (1e-3, 1e-6)])
 def test_min_separation(ctx, torch_dev, d_min, delta):
     w = W.min_separation(1500, seed=3, d_min=d_min, delta=delta)
