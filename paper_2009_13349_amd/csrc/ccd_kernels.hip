@@ -972,6 +972,11 @@ struct GroupShared {
 // same sequence of binary64 operations as corner_values_axis() for that
 // corner, so the results are those of checking the two boxes one by one.
 //
+// All three coordinates are evaluated: on the levels this runs on, a chunk of
+// 128 boxes where every box already fails after one or two coordinates (the
+// only case where stopping early saves time for a wavefront) practically never
+// occurs, and the wave-wide test for it costs more than it saves.
+//
 // tv, uv, vv: the box's lower and upper ends per axis; on the split axis SPLIT
 // three values lo < mid < hi (child 0 = [lo, mid], child 1 = [mid, hi]).
 template <int KIND, int SPLIT>
@@ -986,7 +991,6 @@ __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* E
     double wid0 = 0.0, wid1 = 0.0;
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
-        if (__ballot(col0 || col1) == 0) break;
         const double* xs = Xs + c * 8;
         // corner ranges per group: 0 = child 0 only, 1 = the shared face,
         // 2 = child 1 only (4 corners each); each group starts from its first
@@ -1249,14 +1253,20 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         }
         if (kPacked) {
             // smallest colliding key, every level
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int64_t pos = (e[b] && q[b] < cap) ? q[b] : -1;
-                const uint32_t fl = 1u | (term[b] ? 2u : 0u) | (B.R[b].small ? 4u : 0u);
-                if (col[b] && (!(K.ff & 1u) || B.key[b] < K.f)) {
-                    K.f = B.key[b];
-                    K.ff = fl;
-                    K.fpos = pos;
+            // a lane's second box has the larger key (sibling 1 of a pair): it can
+            // only be the lane's smallest colliding key when the first misses
+            {
+                const int b = col[0] ? 0 : 1;
+                const bool c = col[0] || col[1];
+                const uint64_t key = b ? B.key[1] : B.key[0];
+                const bool eb = b ? e[1] : e[0];
+                const int64_t qb = b ? q[1] : q[0];
+                const bool tb = b ? term[1] : term[0];
+                const bool sb = b ? B.R[1].small : B.R[0].small;
+                if (c && (!(K.ff & 1u) || key < K.f)) {
+                    K.f = key;
+                    K.ff = 1u | (tb ? 2u : 0u) | (sb ? 4u : 0u);
+                    K.fpos = (eb && qb < cap) ? qb : -1;
                 }
             }
             // largest colliding key: only on a level where m_I can stop
