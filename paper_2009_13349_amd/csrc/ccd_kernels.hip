@@ -1103,6 +1103,9 @@ struct LaneBoxes {
 // checked from LDS.  f is then known exactly (every key below it has been
 // checked), its rank comes from a count, and if decide_first() ends the query
 // the pass returns early with that outcome; otherwise it goes on unchanged.
+// The chunk loop leaves at that chunk and the head try runs outside it, then a
+// second loop takes the remaining chunks: the rarely run head-try code is then
+// not part of the hot loop (which spills less for it).
 template <int W, int KIND, int FIN, int SPLIT, bool OP>
 __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
                                            int64_t cap, const State& S, int64_t words,
@@ -1191,7 +1194,9 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
 
     uint64_t p0 = 0, p1 = 0, p2 = 0;  // software pipelining: the next chunk loads early
     if (tid < words) load(tid, p0, p1, p2);
-    for (int64_t b0 = 0; b0 < words; b0 += T) {
+    // one chunk of T words: check, accumulate, store the next level; returns
+    // whether a colliding box of it could end the query (head try)
+    auto chunk = [&](int64_t b0) -> bool {
         const int64_t i = b0 + tid;
         const bool act = i < words;
         LaneBoxes B;
@@ -1308,83 +1313,98 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
                 }
             }
         }
+        bool found = false;
         if (kHead && !tried) {
             bool ends = false;
 #pragma unroll
             for (int b = 0; b < 2; ++b)
                 ends = ends || (col[b] && (term[b] || cap_level ||
                                            (!literal && S.tpend <= L.tmax * B.t0[b])));
-            if (__ballot(ends) != 0) {
-                tried = true;
-                KeyAcc F = K;
-                keyacc_reduce(F);
-                const uint64_t g = F.f;
-                const int64_t done = b0 + T < words ? b0 + T : words;
-                // unchecked words holding a key below g, gathered in LDS
-                uint32_t nc = 0;
-                bool fits = true;
-                for (int64_t j0 = done; j0 < words; j0 += T) {
-                    const int64_t j = j0 + lane;
-                    const uint64_t wd = j < words ? ct[j] : 0;
-                    const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
-                    const bool below = j < words && k0 < g;
-                    const uint64_t m = __ballot(below);
-                    if (m) {
-                        const uint32_t c = (uint32_t)__popcll(m);
-                        if (nc + c > 64) { fits = false; break; }
-                        if (below) sh.cand[nc + __popcll(m & lt)] = wd;
-                        nc += c;
-                    }
-                }
-                if (fits) {
-                    __syncthreads();  // one wavefront: orders the LDS writes before the reads
-                    const bool cact = (uint32_t)lane < nc;
-                    const uint64_t cw = cact ? sh.cand[lane] : 0;
-                    LaneBoxes C;
-                    expand(cact, cw, 0, 0, C);
-                    check(C);
-                    KeyAcc G;
-                    keyacc_init(G);
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        if (C.R[b].collide)
-                            keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small,
-                                       false, -1);
-                    keyacc_reduce(G);
-                    keyacc_merge(F, G);
-                    const uint64_t f = F.f;  // the level's first colliding key
-                    // rank of f: keys below it among checked words and candidates
-                    unsigned long long r = 0;
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) r += (C.act[b] && C.key[b] < f) ? 1 : 0;
-                    for (int64_t j = lane; j < done; j += T) {
-                        const uint64_t wd = ct[j];
-                        if (kPair) {
-                            const uint64_t k0 = pair_child(wd, psx, plowx, 0);
-                            r += k0 < f ? 1 : 0;
-                            r += ((wd & kPairFlag) && (k0 | (1ull << psx)) < f) ? 1 : 0;
-                        } else {
-                            r += wd < f ? 1 : 0;
-                        }
-                    }
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
-                    const uint64_t rf = uni64(r);
-                    Acc Fa;
-                    acc_init(Fa);
-                    kc.decode(f, Fa.ft, Fa.fu, Fa.fv);
-                    Fa.fflags = F.ff;
-                    const Outcome O = decide_first(Fa, S, literal, max_iter, L, rf);
-                    if (O.finish) {
-                        early = true;
-                        Oe = O;
-                        checked = boxes_done + (uint64_t)(__popcll(__ballot(C.act[0])) +
-                                                          __popcll(__ballot(C.act[1])));
-                        return;
-                    }
-                }
+            found = __ballot(ends) != 0;
+        }
+        return found;
+    };
+    int64_t b0 = 0;
+    bool found = false;
+    for (; b0 < words; b0 += T) {
+        if (chunk(b0)) {
+            found = true;
+            b0 += T;
+            break;
+        }
+    }
+    if (kHead && found) {
+        tried = true;
+        const uint64_t lt = lanemask_lt();
+        KeyAcc F = K;
+        keyacc_reduce(F);
+        const uint64_t g = F.f;
+        const int64_t done = b0 < words ? b0 : words;
+        // unchecked words holding a key below g, gathered in LDS
+        uint32_t nc = 0;
+        bool fits = true;
+        for (int64_t j0 = done; j0 < words; j0 += T) {
+            const int64_t j = j0 + lane;
+            const uint64_t wd = j < words ? ct[j] : 0;
+            const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
+            const bool below = j < words && k0 < g;
+            const uint64_t m = __ballot(below);
+            if (m) {
+                const uint32_t c = (uint32_t)__popcll(m);
+                if (nc + c > 64) { fits = false; break; }
+                if (below) sh.cand[nc + __popcll(m & lt)] = wd;
+                nc += c;
             }
         }
+        if (fits) {
+            __syncthreads();  // one wavefront: orders the LDS writes before the reads
+            const bool cact = (uint32_t)lane < nc;
+            const uint64_t cw = cact ? sh.cand[lane] : 0;
+            LaneBoxes C;
+            expand(cact, cw, 0, 0, C);
+            check(C);
+            KeyAcc G;
+            keyacc_init(G);
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                if (C.R[b].collide)
+                    keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small,
+                               false, -1);
+            keyacc_reduce(G);
+            keyacc_merge(F, G);
+            const uint64_t f = F.f;  // the level's first colliding key
+            // rank of f: keys below it among checked words and candidates
+            unsigned long long r = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) r += (C.act[b] && C.key[b] < f) ? 1 : 0;
+            for (int64_t j = lane; j < done; j += T) {
+                const uint64_t wd = ct[j];
+                if (kPair) {
+                    const uint64_t k0 = pair_child(wd, psx, plowx, 0);
+                    r += k0 < f ? 1 : 0;
+                    r += ((wd & kPairFlag) && (k0 | (1ull << psx)) < f) ? 1 : 0;
+                } else {
+                    r += wd < f ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+            const uint64_t rf = uni64(r);
+            Acc Fa;
+            acc_init(Fa);
+            kc.decode(f, Fa.ft, Fa.fu, Fa.fv);
+            Fa.fflags = F.ff;
+            const Outcome O = decide_first(Fa, S, literal, max_iter, L, rf);
+            if (O.finish) {
+                early = true;
+                Oe = O;
+                checked = boxes_done + (uint64_t)(__popcll(__ballot(C.act[0])) +
+                                                  __popcll(__ballot(C.act[1])));
+                return;
+            }
+        }
+        // the head try did not end the query: the level goes on
+        for (; b0 < words; b0 += T) (void)chunk(b0);
     }
     checked = S.cnt;
     if (kPacked) {
