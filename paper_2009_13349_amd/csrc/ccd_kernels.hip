@@ -1127,7 +1127,9 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
     const uint64_t lowx = mask64(sx);
     const int psx = kPair ? field_shift(SPLIT, kc) : 0;  // split field of the stored parents
     const uint64_t plowx = mask64(psx);
-    const double half_u = 0.5 * L.wu, half_v = 0.5 * L.wv;
+    // child 1's offset of u_lo and v_lo on this level's split axis (adding 0.0 is
+    // exact, so one formula serves the three axes)
+    const double du1 = axis == 1 ? 0.5 * L.wu : 0.0, dv1 = axis == 2 ? 0.5 * L.wv : 0.0;
     const double wsp = SPLIT == 0 ? L.wt : (SPLIT == 1 ? L.wu : L.wv);
     KeyAcc K;  // packed input
     if (kPacked) keyacc_init(K);
@@ -1211,12 +1213,9 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
             col[b] = B.R[b].collide;
             term[b] = B.R[b].small || L.dcap;
             e[b] = col[b] && !term[b];
-            adm[b] = true;
-            if (KIND == kVF && axis != 0) {
-                const double cu = axis == 1 ? B.u0[b] + half_u : B.u0[b];
-                const double cv = axis == 2 ? B.v0[b] + half_v : B.v0[b];
-                adm[b] = cu + cv <= 1.0;
-            }
+            // vertex-face prism test of child 1; on a t split its (u_lo, v_lo) is
+            // the box's own, which passed when the box was made
+            adm[b] = KIND != kVF || (B.u0[b] + du1) + (B.v0[b] + dv1) <= 1.0;
         }
         // positions of what this lane stores for the next level
         const uint64_t lt = lanemask_lt();
