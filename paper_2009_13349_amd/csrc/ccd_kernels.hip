@@ -666,10 +666,13 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
     }
 
     while (true) {
+        // idle lanes take new queries together, once a quarter of the wave is
+        // idle: the queries' scattered coordinate loads then cost the wave one
+        // memory latency for many lanes instead of one per finished query
         if (PERSISTENT && !exhausted) {
             const bool need = q < 0;
             const uint64_t m = __ballot(need);
-            if (m) {
+            if (__popcll(m) >= 16) {
                 const int leader = __builtin_ctzll(m);
                 unsigned long long base = 0;
                 if (lane == leader)
