@@ -933,18 +933,42 @@ __device__ __forceinline__ void keyacc_merge(KeyAcc& K, const KeyAcc& B) {
     if (B.th && (!K.th || B.tm < K.tm)) { K.tm = B.tm; K.th = 1; }
 }
 
-// Wavefront reduction; the result is made wave-uniform.
-__device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        KeyAcc B;
-        B.f = __shfl_xor(K.f, off); B.m = __shfl_xor(K.m, off); B.tm = __shfl_xor(K.tm, off);
-        B.fpos = __shfl_xor(K.fpos, off); B.ff = __shfl_xor(K.ff, off);
-        B.mh = __shfl_xor(K.mh, off); B.th = __shfl_xor(K.th, off);
-        keyacc_merge(K, B);
+        const uint64_t y = __shfl_xor(x, off);
+        x = y < x ? y : x;
     }
-    K.f = uni64(K.f); K.m = uni64(K.m); K.tm = uni64(K.tm); K.fpos = uni64s(K.fpos);
-    K.ff = uni32(K.ff); K.mh = uni32(K.mh); K.th = uni32(K.th);
+    return uni64(x);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t y = __shfl_xor(x, off);
+        x = y > x ? y : x;
+    }
+    return uni64(x);
+}
+
+// Wavefront reduction; the result is made wave-uniform.  Keys of one level are
+// distinct, so the smallest one is held by exactly one lane, which supplies its
+// flags and position.
+__device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
+    const bool hf = (K.ff & 1u) != 0;
+    const uint64_t g = wave_min_u64(hf ? K.f : ~0ull);
+    const uint64_t hold = __ballot(hf && K.f == g);
+    const int l = hold ? __builtin_ctzll(hold) : 0;
+    const uint32_t ff = uni32((uint32_t)__shfl((int)K.ff, l));
+    const int64_t fpos = uni64s(__shfl(K.fpos, l));
+    const uint64_t mh = __ballot(K.mh != 0), th = __ballot(K.th != 0);
+    const uint64_t m = wave_max_u64(K.mh ? K.m : 0ull);
+    const uint64_t tm = wave_min_u64(K.th ? K.tm : ~0ull);
+    K.f = hold ? g : ~0ull;
+    K.ff = hold ? ff : 0u;
+    K.fpos = hold ? fpos : -1;
+    K.m = mh ? m : 0ull; K.mh = mh ? 1u : 0u;
+    K.tm = th ? tm : ~0ull; K.th = th ? 1u : 0u;
 }
 
 // Storage formats of a level in a group arena buffer.
