@@ -93,6 +93,20 @@ def test_tmax_parity_through_group_engines(ctx, torch_dev, t_max):
             assert_same(got, ref, f"t_max {t_max} literal {literal} tuning {tune}")
 
 
+@pytest.mark.parametrize("t_max", [0.5, 0.0625])
+def test_tmax_with_min_separation(ctx, torch_dev, t_max):
+    """The shortened interval together with a minimum separation (Sec. 5 and
+    Sec. 6 combined)."""
+    d_min, delta = 1e-3, 1e-4
+    w = W.min_separation(2000, seed=58, d_min=d_min, delta=delta)
+    ref = oracle.solve_batch(w["pos"], w["kind"], delta=delta, max_iter=100_000, min_sep=d_min,
+                             t_max=t_max)
+    for engine in (0, 1):
+        got, _ = run_gpu(ctx, torch_dev, w, engine, delta=delta, max_iter=100_000, min_sep=d_min,
+                         t_max=t_max)
+        assert_same(got, ref, f"t_max {t_max} min_sep {d_min} engine {engine}")
+
+
 def test_tmax_single_queries(ccdmod, torch_dev):
     w = W.concat([W.uniform_vf(40, seed=56), W.edge_edge_mixed(40, seed=57)])
     for i in range(w["pos"].shape[1]):
