@@ -953,7 +953,9 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
 
 // Wavefront reduction; the result is made wave-uniform.  Keys of one level are
 // distinct, so the smallest one is held by exactly one lane, which supplies its
-// flags and position.
+// flags and position; the largest key and the smallest terminal time index are
+// plain maximum / minimum reductions (lanes without one contribute the
+// identity).
 __device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
     const bool hf = (K.ff & 1u) != 0;
     const uint64_t g = wave_min_u64(hf ? K.f : ~0ull);
