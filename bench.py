@@ -300,9 +300,9 @@ def main():
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the root finder has no cross-GPU step in this "
-              "build (queries are independent; sharding is a partition of the query index).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: queries are independent, so several GPUs would "
+              "each run the same batch call on a slice of the query index, with no cross-GPU "
+              "step to measure.", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
