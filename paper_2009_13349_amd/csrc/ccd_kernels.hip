@@ -1152,8 +1152,6 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
     KeyCodec kc;
     kc.init(S.d[1], S.d[2]);
     const int axis = L.axis;
-    const int sx = field_shift(axis, kc);  // < 64 when OP
-    const uint64_t lowx = mask64(sx);
     const int psx = kPair ? field_shift(SPLIT, kc) : 0;  // split field of the stored parents
     const uint64_t plowx = mask64(psx);
     // child 1's offset of u_lo and v_lo on this level's split axis (adding 0.0 is
@@ -1247,7 +1245,6 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
             adm[b] = KIND != kVF || (B.u0[b] + du1) + (B.v0[b] + dv1) <= 1.0;
         }
         // positions of what this lane stores for the next level
-        const uint64_t lt = lanemask_lt();
         int64_t q[2];
         unsigned long long wtot, btot;
         uint64_t mk[4];
