@@ -607,7 +607,6 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
     if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = d->n;
-    const bool persistent = ctx->engine == CCD_ENGINE_PERSISTENT;
 
     // batch-level parameter checks that do not depend on the queries
     int64_t mi_max = d->params.max_iter;
