@@ -771,7 +771,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
     struct Knob { int id; std::vector<int64_t> vals; };
     const std::vector<Knob> knobs = {
         {0, {2, 3, 4}},            // group_occupancy (with group_count = 4 * cu * occ)
-        {1, {32, 64, 128, 256, 512}},  // lane_budget
+        {1, {32, 64, 128, 192, 256, 384, 512}},  // lane_budget
         {2, {16, 32, 64}},         // lane_capacity
         {3, {4, 8, 12}},           // lane_waves_per_cu
         {4, {1, 2}},               // group_waves
