@@ -207,7 +207,7 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
 
 
 def measure_extras(ctx, torch, pos, kind, w, n, steps):
-    """The line search's shortened interval (Sec. 6): the same queries over t in
+    """The line search's shortened interval (Sec. 7.2): the same queries over t in
     [0, 0.5], then the batch-wide smallest toi (the step bound); the indexed
     form with a scene-wide filter; and the host-pointer form."""
     from paper_2009_13349_amd import ccd
@@ -247,7 +247,7 @@ def measure_host(ctx, w, n, runs: int = 2):
 
 def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
     """Candidate pairs over shared vertex arrays with a scene-wide filter (the
-    mesh form of Sec. 6): a two-sheet mesh scene of n_pairs broad-phase pairs,
+    mesh form of Sec. 7): a two-sheet mesh scene of n_pairs broad-phase pairs,
     gamma from ccd_scene_gamma, then ccd_batch_indexed (gather + root finder)."""
     from paper_2009_13349_amd import ccd, workloads as W
     s = W.mesh_scene(n_pairs, seed=5)

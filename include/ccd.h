@@ -10,14 +10,14 @@
  *
  *   - the problem is a root of F_vf or F_ee on Omega (Sec. 3, eqs. F-vf, F-ee);
  *   - a box I of the (t, u, v) domain is tested with the axis-aligned box of F
- *     at the 8 corners of I (Sec. 4.2, eq. box) against the floating-point
- *     filter eps_c = K gamma_c^3 (Sec. 4.2, eq. ccd-error);
+ *     at the 8 corners of I (Sec. 5.2, eq. box) against the floating-point
+ *     filter eps_c = K gamma_c^3 (Sec. 5.2, eq. ccd-error);
  *   - boxes are bisected breadth first, level by level, along the axis with
  *     the largest estimated co-domain extent (Alg. 2, SPLIT; eq. kappas) until
  *     the first colliding box of a level is smaller than delta or inside the
  *     filter cube, or until m_I boxes have been checked (Alg. 2);
  *   - with a minimum separation d > 0 the box is enlarged by d and the filter
- *     constants change (Sec. 5.1, eq. msccd-error); distances are L-infinity.
+ *     constants change (Sec. 6.1, eq. msccd-error); distances are L-infinity.
  *
  * All arithmetic is IEEE binary64 with no contraction; results are bit-for-bit
  * reproducible and independent of batch composition, launch shape and tuning.
@@ -29,13 +29,13 @@
  *     EE: p1, p2 (edge A) and p3, p4 (edge B).
  *   - A query is invalid if a coordinate is not finite or exceeds 1e300 in
  *     magnitude, delta is not a positive finite number, max_iter < 1, min_sep is
- *     negative or not finite, min_sep is not below min_c gamma_c (Sec. 5.1
+ *     negative or not finite, min_sep is not below min_c gamma_c (Sec. 6.1
  *     assumes d < gamma).  A batch is rejected (CCD_EINVAL) when t_max is not
  *     in (0, 1].
  *   - Output convention (Alg. 2): hit = (toi <= 1); no collision is
  *     toi = +inf, t_width = 0.  toi is a conservative (never late) estimate of
  *     the earliest contact time; t_width is w(I_t) of the level it came from.
- *   - Shortened time interval (Sec. 6, line search: only the initial interval
+ *   - Shortened time interval (Sec. 7.2, line search: only the initial interval
  *     of Alg. 2 changes): with t_max < 1 the search covers t in [0, t_max].  The
  *     time axis is bisected in s = t / t_max and a box's time endpoints are
  *     fl(t_max * s); toi is such an endpoint and t_width = t_max * 2^-depth.
@@ -81,7 +81,7 @@ extern "C" {
                                  candidate is left, which keeps toi conservative when
                                  the first box's region later turns out empty. */
 
-/* Parameters of one query (Alg. 2 inputs; Sec. 5.1 adds min_sep). */
+/* Parameters of one query (Alg. 2 inputs; Sec. 6.1 adds min_sep). */
 typedef struct ccd_params {
     double delta;      /* tolerance delta > 0 on the co-domain width; paper default 1e-6 */
     int64_t max_iter;  /* m_I >= 1: maximum number of box checks; paper default 1e6 */
@@ -241,7 +241,7 @@ int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
 
 /*
  * Smallest toi of a batch, for a line search: the step length is bounded by
- * the earliest time of impact over the candidate pairs (Sec. 6, Alg. 4: alpha
+ * the earliest time of impact over the candidate pairs (Sec. 7.2, Alg. 4: alpha
  * = min(t, alpha) over the MSCCD calls).  toi: n device doubles (a result's
  * toi array); out: one device double, 8-byte aligned.  Asynchronous on
  * `stream` (0 = default), ordered after the batch that wrote toi when issued
@@ -252,7 +252,7 @@ int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
 int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, void* stream);
 
 /*
- * Candidate pairs over shared vertex arrays (Sec. 6: the active-set and line
+ * Candidate pairs over shared vertex arrays (Sec. 7: the active-set and line
  * search drivers run CCD on the pairs of a mesh's broad phase), with an
  * optional scene-wide filter.
  *
@@ -260,7 +260,7 @@ int ccd_min_toi(ccd_context* ctx, const double* toi, int64_t n, double* out, voi
  * v1 (at t = 1): VF (p, v1, v2, v3), EE (p1, p2, p3, p4).  An id outside
  * [0, n_vertices) makes the query invalid (status CCD_ST_INVALID).
  *
- * gamma: NULL, or 3 doubles, the scene-wide gamma per axis.  Sec. 6 computes
+ * gamma: NULL, or 3 doubles, the scene-wide gamma per axis.  Sec. 7 computes
  * the tolerances of eq. ccd-error / msccd-error from the maximum over all the
  * vertices of the scene, so that they are the same for every query of a step;
  * eps_c = K gamma_c^3 then replaces the query's own.  A query whose own gamma

@@ -2,7 +2,7 @@
 
 This package is the plain, slow, single-threaded reference implementation of
 Algorithm 2 of Wang et al. 2021 (with the minimum-separation variant of its
-Sec. 5) that the GPU library is checked against, plus an exact-rational checker
+Sec. 6) that the GPU library is checked against, plus an exact-rational checker
 (`oracle.exact`).  Only the test-suite, the smoke check and the CPU-baseline leg
 of the benchmark may import it; the product library never does.  It shares no
 source with the HIP library.

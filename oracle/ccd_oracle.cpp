@@ -14,10 +14,10 @@
 // Structure follows the paper:
 //   * linear trajectories p(t) = (1-t) p0 + t p1                  (Sec. 3, Preliminaries)
 //   * F_vf and F_ee                                               (Sec. 3, eqs. F-vf, F-ee)
-//   * box inclusion B_F(I): AABB of F at the 8 corners of I        (Sec. 4.2, eq. box)
-//   * floating-point filter eps = K * gamma^3                      (Sec. 4.2, eq. ccd-error)
-//   * minimum-separation filter and enlarged box                   (Sec. 5.1, eq. msccd-error)
-//   * kappa_t, kappa_u, kappa_v and the split rule                 (Sec. 4.2, eq. kappas; Alg. 2 SPLIT)
+//   * box inclusion B_F(I): AABB of F at the 8 corners of I        (Sec. 5.2, eq. box)
+//   * floating-point filter eps = K * gamma^3                      (Sec. 5.2, eq. ccd-error)
+//   * minimum-separation filter and enlarged box                   (Sec. 6.1, eq. msccd-error)
+//   * kappa_t, kappa_u, kappa_v and the split rule                 (Sec. 5.2, eq. kappas; Alg. 2 SPLIT)
 //   * SOLVE with a priority queue ordered by (level, t)            (Alg. 2)
 //
 // Readings where the paper is silent or ambiguous (each one also appears in the
@@ -35,12 +35,12 @@
 //     is already at depth 52 is treated as terminal, so every endpoint and every
 //     complement 1-t, 1-u, (1-u)-v stays exact (1-t only while t_max = 1).
 //   * n_checks is reported saturated at m_I.
-//   * shortened time interval (Sec. 6, line search: only the initial I changes):
+//   * shortened time interval (Sec. 7.2, line search: only the initial I changes):
 //     I_t = [0, t_max], 0 < t_max <= 1, bisected in the normalized coordinate
 //     s = t / t_max; a box's time endpoints are fl(t_max * s) and its width is
 //     w(I_t) = t_max * w(I_s) (exact).  kappa keeps eq. kappas (corners at
 //     t = 0 and t = 1: a per-unit slope).  ORDER compares s, which orders like t.
-//   * scene-wide filter (Sec. 6: eps from the maximum over all the vertices of
+//   * scene-wide filter (Sec. 7: eps from the maximum over all the vertices of
 //     the scene): an optional gamma per axis replaces the query's own; it must
 //     be at least the query's gamma (else the filter's bound does not cover the
 //     query, which is then invalid), and d < min_c gamma_c uses it.
@@ -114,7 +114,7 @@ int oracle_F(int kind, const double X[24], double t, double u, double v, double 
     return ORACLE_OK;
 }
 
-// Sec. 4.2 eq. ccd-error and Sec. 5.1 eq. msccd-error: eps_c = K gamma_c^3 with
+// Sec. 5.2 eq. ccd-error and Sec. 6.1 eq. msccd-error: eps_c = K gamma_c^3 with
 // gamma_c = max(x_max, 1). The paper prints K in decimal; the values are the
 // exact binary numbers 28, 30, 32 and 34 times 2^-52.
 void oracle_filter(int kind, const double X[24], double min_sep, double eps[3]) {
@@ -152,7 +152,7 @@ static double gamma_min(const double X[24]) {
     return gmin;
 }
 
-// Sec. 4.2 eq. kappas, with u_i, v_j, t_i ranging over {0, 1}:
+// Sec. 5.2 eq. kappas, with u_i, v_j, t_i ranging over {0, 1}:
 //   kappa_t = 3 max ||F(0,u,v) - F(1,u,v)||_inf, and likewise for u and v.
 void oracle_kappa(int kind, const double X[24], double kappa[3]) {
     double Fc[2][2][2][3];
@@ -190,7 +190,7 @@ int oracle_split_axis(const double kappa[3], const double width[3]) {
     return 2;
 }
 
-// Sec. 4.2 eq. box plus the filter test, and Sec. 5.1 for d > 0.
+// Sec. 5.2 eq. box plus the filter test, and Sec. 6.1 for d > 0.
 //   box = {t_lo, t_hi, u_lo, u_hi, v_lo, v_hi}
 //   collide: B enlarged by d meets C_eps;  inside: B enlarged by d lies in C_eps;
 //   width: w(B) of the un-enlarged box.
@@ -232,7 +232,7 @@ int oracle_validate(const double X[24], double delta, int64_t max_iter, double m
     if (!(delta > 0.0) || !std::isfinite(delta)) return ORACLE_EINVAL;
     if (max_iter < 1) return ORACLE_EINVAL;
     if (!(min_sep >= 0.0) || !std::isfinite(min_sep)) return ORACLE_EINVAL;
-    if (!(min_sep < gamma_min(X))) return ORACLE_EINVAL;   // Sec. 5.1: d < gamma
+    if (!(min_sep < gamma_min(X))) return ORACLE_EINVAL;   // Sec. 6.1: d < gamma
     return ORACLE_OK;
 }
 

@@ -7,7 +7,7 @@ predicate is decided exactly.  Two independent routes are provided:
 * the multivariate definition (Sec. 3, eqs. F-vf / F-ee): a root of F in the
   domain Omega means contact.  `exclusion_proof` bisects the parameter box and
   uses the exact corner hull of F (F is affine in each of t, u, v separately, so
-  on a box each coordinate of F attains its extremes at the 8 corners, Sec. 4.2
+  on a box each coordinate of F attains its extremes at the 8 corners, Sec. 5.2
   Prop. 1) to certify that no root exists;
 * the univariate coplanarity formulation (Sec. 3, eq. univariate): contact can
   only happen at a root of the cubic f(t) = <n(t), q(t)>, followed by an
@@ -62,7 +62,7 @@ def corner_hull(kind, P, box):
 
 
 def _excluded(lo, hi, d):
-    # F(box) misses the cube [-d, d]^3 (L-infinity distance d, Sec. 5.1).
+    # F(box) misses the cube [-d, d]^3 (L-infinity distance d, Sec. 6.1).
     return any(lo[c] > d or hi[c] < -d for c in range(3))
 
 

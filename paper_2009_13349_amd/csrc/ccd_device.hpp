@@ -10,7 +10,7 @@
 // The complements 1-u and (1-u)-v are exact (u, v endpoints are dyadic with at
 // most 52 fractional bits), and so is 1-t on the full time interval; on a
 // shortened interval [0, t_max] the time values fl(t_max s) are not dyadic and
-// 1-t is rounded once, which the static filter of Sec. 4.2 (derived for any
+// 1-t is rounded once, which the static filter of Sec. 5.2 (derived for any
 // inputs in [0,1]) still covers.
 //
 // Boxes are integer dyadic triples: on a level with per-axis bisection depths
@@ -123,7 +123,7 @@ struct CheckResult {
     bool small;    // w(B) < delta, or B (enlarged by d) inside the filter cube
 };
 
-// Box check of Sec. 4.2 (eq. box, filter test) and Sec. 5.1 (enlargement by d).
+// Box check of Sec. 5.2 (eq. box, filter test) and Sec. 6.1 (enlargement by d).
 // With want_kappa the box must be [0,1]^3 and kappa (eq. kappas) is produced
 // from the same corner values.
 template <int KIND>
@@ -212,7 +212,7 @@ __device__ __forceinline__ bool vf_admit(uint64_t iu, int du, uint64_t iv, int d
     return a + b <= (1ull << D);
 }
 
-// Scene-wide filter (Sec. 6: tolerances from the maximum over all the vertices
+// Scene-wide filter (Sec. 7: tolerances from the maximum over all the vertices
 // of the scene): eps_c = K gamma_c^3 with the given gamma, valid for a query
 // only if gamma_c is at least the query's own gamma_c (then the filter's bound
 // covers it).  Returns false otherwise; gamma_min as filter_eps().

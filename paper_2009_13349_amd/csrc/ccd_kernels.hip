@@ -339,7 +339,7 @@ __device__ __forceinline__ CheckResult check_any(const Query& Q, const LevelInfo
 // Group-engine box check: the query's coordinates sit in LDS as Xs[c*8 + k]
 // (one query per block), axes are evaluated one after the other and the
 // remaining axes are skipped once no active lane of the wavefront still
-// collides (Sec. 4.2: "check one axis at a time and return early").  The
+// collides (Sec. 5.2, efficient evaluation: per-axis early exit).  The
 // values are the same as box_check()'s.
 template <int KIND>
 __device__ __forceinline__ CheckResult check_box_lds(const double* Xs, const double* Es,
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(512) void k_root(BatchArgs a, int64_t* order) {
 }
 
 // Candidate pairs given as vertex ids over shared vertex arrays (the active-set
-// and line-search drivers of Sec. 6 work on a mesh): the 8 points of query q
+// and line-search drivers of Sec. 7 work on a mesh): the 8 points of query q
 // are gathered into the structure-of-arrays layout pos[(3k+c)*n + q].  An id
 // outside [0, nv) gives the query NaN coordinates, which makes it invalid.
 __global__ void k_gather(int64_t n, const double* v0, const double* v1, const int32_t* ids,
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_scene_gamma(const double* v0, const dou
 }
 
 // Smallest toi of a batch: the line search bounds its step by the earliest time
-// of impact (alpha = min over the candidates, Sec. 6).  toi values are +0..1,
+// of impact (alpha = min over the candidates, Sec. 7).  toi values are +0..1,
 // +inf or NaN (invalid queries, skipped); the bit patterns of non-negative
 // doubles order like their values, so an integer atomic min gives the result.
 __global__ void k_min_toi_init(unsigned long long* out) {
@@ -1718,7 +1718,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         }
         __syncthreads();
         if (tid < 3) {
-            // gamma_c and eps_c (Sec. 4.2); min_sep > 0 selects the Sec. 5.1 constants
+            // gamma_c and eps_c (Sec. 5.2); min_sep > 0 selects the Sec. 6.1 constants
             const double K = filter_constant(kind, min_sep);
             double gm = 1.0;
             for (int k = 0; k < 8; ++k) gm = fmax(gm, fabs(sh.Xs[tid * 8 + k]));

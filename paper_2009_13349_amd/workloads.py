@@ -538,7 +538,7 @@ def concat(ws) -> dict:
 
 # ---------------------------------------------------------------------------
 # Candidate pairs over shared vertex arrays (the mesh form the active-set and
-# line-search drivers of Sec. 6 work on).
+# line-search drivers of Sec. 7 work on).
 
 def as_indexed(w: dict) -> dict:
     """The queries of a structure-of-arrays workload as vertex arrays and ids:

@@ -1,5 +1,5 @@
 """GPU <-> oracle parity of candidate pairs over shared vertex arrays and of
-the scene-wide filter (Sec. 6), called through the C ABI.  Bar: every output
+the scene-wide filter (Sec. 7), called through the C ABI.  Bar: every output
 bit-identical."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
 """GPU <-> oracle parity of the shortened time interval [0, t_max] (the line
-search's change to Alg. 2's initial interval, Sec. 6) and of the batch-wide
+search's change to Alg. 2's initial interval, Sec. 7.2) and of the batch-wide
 smallest toi used to bound the step length.  Same bar as the other parity
 tests: every output bit-identical."""
 import math
@@ -95,8 +95,8 @@ def test_tmax_parity_through_group_engines(ctx, torch_dev, t_max):
 
 @pytest.mark.parametrize("t_max", [0.5, 0.0625])
 def test_tmax_with_min_separation(ctx, torch_dev, t_max):
-    """The shortened interval together with a minimum separation (Sec. 5 and
-    Sec. 6 combined)."""
+    """The shortened interval together with a minimum separation (Sec. 7 and
+    Sec. 7.2 combined)."""
     d_min, delta = 1e-3, 1e-4
     w = W.min_separation(2000, seed=58, d_min=d_min, delta=delta)
     ref = oracle.solve_batch(w["pos"], w["kind"], delta=delta, max_iter=100_000, min_sep=d_min,

@@ -47,7 +47,7 @@ CASES = [
     ("H11_ee_coplanar_slide", EE, q([[0, 0, 0], [1, 0, 0], [.5, 1, 0], [.5, 2, 0]],
                                     [[0, 0, 0], [1, 0, 0], [.5, -1, 0], [.5, 0, 0]]), 0.0,
      "hit_le", 0.5),
-    # L-infinity minimum separation (Sec. 5): the point passes the vertex v1 at
+    # L-infinity minimum separation (Sec. 6): the point passes the vertex v1 at
     # (-7/8 d, -7/8 d) in the plane z = 0: Euclidean distance 1.24 d > d, but
     # L-infinity distance 7/8 d <= d, reached for |z| <= d, i.e. t >= 1/2 - d/2.
     ("H12_ms_linf_hit", VF, q([[-.875 * D, -.875 * D, 1]] + TRI, [[-.875 * D, -.875 * D, -1]] + TRI),
@@ -138,7 +138,7 @@ def test_min_separation_no_false_negatives(orc, X, kind):
 
 def test_accuracy_of_width_terminated_returns(orc):
     """A box returned by the width or inside test satisfies, exactly at its 8
-    corners, |F^c| <= d + delta (1 + 2^-52) + 2 eps_c (filter bound of Sec. 4.2)."""
+    corners, |F^c| <= d + delta (1 + 2^-52) + 2 eps_c (filter bound of Sec. 5.2)."""
     from paper_2009_13349_amd import workloads as W
     w = W.uniform_vf(256, seed=7)
     checked = 0

@@ -21,7 +21,7 @@ def q(p0, p1):
 
 
 # ---------------------------------------------------------------------------
-# Filter constants (Sec. 4.2 eq. ccd-error, Sec. 5.1 eq. msccd-error)
+# Filter constants (Sec. 5.2 eq. ccd-error, Sec. 6.1 eq. msccd-error)
 
 def _golden_constants():
     out = {}
@@ -143,7 +143,7 @@ def test_F_vanishes_at_constructed_root(orc, kind):
 
 
 # ---------------------------------------------------------------------------
-# Error bound of the filter (Sec. 4.2): |fl(F) - F| <= eps on every axis
+# Error bound of the filter (Sec. 5.2): |fl(F) - F| <= eps on every axis
 
 @pytest.mark.parametrize("kind", [VF, EE])
 def test_filter_bounds_rounding_error(orc, kind):
@@ -169,7 +169,7 @@ def test_filter_bounds_rounding_error(orc, kind):
 
 
 # ---------------------------------------------------------------------------
-# Propositions of Sec. 4.2 as invariants
+# Propositions of Sec. 5.2 as invariants
 
 @pytest.mark.parametrize("kind", [VF, EE])
 def test_prop1_corner_box_encloses_F(orc, kind):

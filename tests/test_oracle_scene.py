@@ -1,4 +1,4 @@
-"""Pins of the oracle's scene-wide filter (Sec. 6: the tolerances eq.
+"""Pins of the oracle's scene-wide filter (Sec. 7: the tolerances eq.
 ccd-error / msccd-error computed from the maximum over all the vertices of the
 scene).  Reading: a gamma per axis replaces the query's own, and must be at
 least the query's own for the filter's bound to cover the query.  CPU-only."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's shortened time interval I_t = [0, t_max] (Sec. 6: the
+"""Pins of the oracle's shortened time interval I_t = [0, t_max] (Sec. 7.2: the
 line search changes only the initial interval of Alg. 2).  Reading: the time
 axis is bisected in s = t / t_max and a box's time endpoints are
 fl(t_max * s).  The pins use exact arithmetic, exact first contacts and a
