@@ -70,6 +70,13 @@ extern "C" {
 #define CCD_ST_CARRY 0x02   /* returned a remembered terminal box (see CCD_FLAG_LITERAL) */
 #define CCD_ST_DEPTH 0x04   /* returned box was terminal only because a split would
                                go below 2^-52 on its axis */
+#define CCD_ST_OVERFLOW 0x08 /* the next level of the query's frontier did not fit the
+                               scratch the library could give it (the block engine's
+                               arena, see ccd_tuning.block_capacity): the query returned
+                               at the first colliding box of its current level, as Alg. 2
+                               does at the m_I stop, so toi is still conservative (never
+                               later than the first root) but may be earlier than a full
+                               run's; n_checks counts the checks through that level */
 #define CCD_ST_INVALID 0x80 /* device-side validation rejected the query
                                (toi = t_width = NaN, hit = 0, n_checks = 0) */
 
@@ -132,14 +139,15 @@ void ccd_context_destroy(ccd_context* ctx);
 /* Engines selectable with ccd_context_set_engine. */
 #define CCD_ENGINE_PERSISTENT 0 /* persistent kernels: lane per light query, group per
                                    wide query, block per huge query (default) */
-#define CCD_ENGINE_PLAIN 1      /* one thread per query, same fallback tiers */
+#define CCD_ENGINE_PLAIN 1      /* one thread per query for every query up to its lane
+                                   capacity, then the same group and block tiers */
 int ccd_context_set_engine(ccd_context* ctx, int engine);
 
 /* Launch and capacity knobs (what the autotuner searches); 0 keeps a field's
  * current value.  Values are clamped to supported ranges. */
 typedef struct ccd_tuning {
     int32_t lane_waves_per_cu;    /* resident waves per CU of the lane-per-query kernel */
-    int32_t lane_capacity;        /* boxes per level a lane may hold (8..256) */
+    int32_t lane_capacity;        /* boxes per level a lane may hold in LDS (8..32) */
     int64_t lane_budget;          /* checks a lane spends before it hands the query on */
     int32_t group_waves;          /* waves per group working on one wide query (1, 2, 4, 8) */
     int32_t group_count;          /* resident groups of the wide-query kernel */
@@ -147,9 +155,41 @@ typedef struct ccd_tuning {
     int32_t block_count;          /* resident blocks of the huge-query kernel */
     int32_t group_occupancy;      /* single-wave groups: minimum waves per SIMD the register
                                      allocation must allow (1..4) */
+    int64_t block_capacity;       /* words per level of a huge-query arena; 0 (default): 2 m_I + 2,
+                                     enough for every query, clamped to a quarter of the
+                                     budget.  Never below group_capacity.  A query whose
+                                     level outgrows it returns with CCD_ST_OVERFLOW. */
+    int64_t handoff_words;        /* pool (8-byte words) carrying a wide query's current level
+                                     from the group to the block engine; when it is full
+                                     the block engine restarts such a query at level 0
+                                     (same results, more work).  Default 2^25. */
 } ccd_tuning;
 int ccd_context_get_tuning(ccd_context* ctx, ccd_tuning* out);
 int ccd_context_set_tuning(ccd_context* ctx, const ccd_tuning* t);
+
+/*
+ * The scratch a batch of n queries (largest m_I = max_iter) would be given on
+ * a GPU of num_cu compute units under a memory budget (0: the 16 GiB
+ * default) and a tuning (NULL: the defaults; zero fields keep the defaults).
+ * Host-only: touches no device.  Sizes are computed with overflow-checked
+ * arithmetic; the block engine's arena is 2 m_I + 2 words per buffer (enough
+ * for every query, Alg. 2 stops a level below 2 m_I boxes) clamped to a
+ * quarter of the budget and to the tuning's block_capacity.  Returns
+ * CCD_ENOMEM when even one arena of each engine does not fit, CCD_EINVAL for
+ * num_cu < 1, n < 0, max_iter < 1 or an unknown engine.
+ */
+typedef struct ccd_scratch_plan {
+    uint64_t bytes;           /* device memory of the whole plan */
+    uint64_t lane_lds_bytes;  /* LDS per lane-engine block (the lanes' frontiers) */
+    int64_t lane_blocks;
+    int64_t group_count;
+    int64_t group_capacity;   /* words per level buffer */
+    int64_t block_count;
+    int64_t block_capacity;   /* words per level buffer */
+    int64_t handoff_words;
+} ccd_scratch_plan;
+int ccd_plan_scratch(const ccd_tuning* tuning, int num_cu, size_t mem_budget_bytes, int64_t n,
+                     int64_t max_iter, int engine, ccd_scratch_plan* out);
 
 
 /* A batch of n queries in structure-of-arrays layout. */
@@ -235,6 +275,11 @@ typedef struct ccd_stats {
                                 fraction of SIMD lanes doing box checks */
     float kernel_ms[4];      /* device time of [root pass, lane, group, block] kernels
                                 (only when timing is enabled, else 0) */
+    uint32_t reserved;
+    uint64_t overflowed;     /* queries returned with CCD_ST_OVERFLOW */
+    uint64_t restarted;      /* group -> block hand-offs restarted at level 0 (pool full) */
+    uint64_t deep;           /* lane -> group hand-offs because a level reached depth sum 64 */
+    uint64_t handoff_words;  /* pool words the group -> block hand-offs asked for */
 } ccd_stats;
 int ccd_context_enable_timing(ccd_context* ctx, int enable);
 int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);

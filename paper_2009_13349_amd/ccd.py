@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libccd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 KIND_VF, KIND_EE = 0, 1
-ST_CAP, ST_CARRY, ST_DEPTH, ST_INVALID = 0x01, 0x02, 0x04, 0x80
+ST_CAP, ST_CARRY, ST_DEPTH, ST_OVERFLOW, ST_INVALID = 0x01, 0x02, 0x04, 0x08, 0x80
 FLAG_LITERAL = 0x1
 ENGINE_PERSISTENT, ENGINE_PLAIN = 0, 1
 
@@ -28,7 +28,7 @@ EXPORTED = [
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
     "ccd_context_enable_graphs", "ccd_context_graph_counts", "ccd_autotune",
     "ccd_tuning_cache_store", "ccd_tuning_cache_load", "ccd_min_toi", "ccd_batch_indexed",
-    "ccd_scene_gamma",
+    "ccd_scene_gamma", "ccd_plan_scratch",
 ]
 
 
@@ -58,7 +58,15 @@ class Tuning(ctypes.Structure):
     _fields_ = [("lane_waves_per_cu", ctypes.c_int32), ("lane_capacity", ctypes.c_int32),
                 ("lane_budget", ctypes.c_int64), ("group_waves", ctypes.c_int32),
                 ("group_count", ctypes.c_int32), ("group_capacity", ctypes.c_int64),
-                ("block_count", ctypes.c_int32), ("group_occupancy", ctypes.c_int32)]
+                ("block_count", ctypes.c_int32), ("group_occupancy", ctypes.c_int32),
+                ("block_capacity", ctypes.c_int64), ("handoff_words", ctypes.c_int64)]
+
+
+class ScratchPlan(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64), ("lane_lds_bytes", ctypes.c_uint64),
+                ("lane_blocks", ctypes.c_int64), ("group_count", ctypes.c_int64),
+                ("group_capacity", ctypes.c_int64), ("block_count", ctypes.c_int64),
+                ("block_capacity", ctypes.c_int64), ("handoff_words", ctypes.c_int64)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -84,7 +92,10 @@ class ResultSoA(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("checks", (ctypes.c_uint64 * 2) * 3), ("promoted", ctypes.c_uint64 * 2),
-                ("lane_slots", ctypes.c_uint64 * 3), ("kernel_ms", ctypes.c_float * 4)]
+                ("lane_slots", ctypes.c_uint64 * 3), ("kernel_ms", ctypes.c_float * 4),
+                ("reserved", ctypes.c_uint32), ("overflowed", ctypes.c_uint64),
+                ("restarted", ctypes.c_uint64), ("deep", ctypes.c_uint64),
+                ("handoff_words", ctypes.c_uint64)]
 
 
 _LIB = None
@@ -128,6 +139,8 @@ def _lib():
         L.ccd_min_toi.argtypes = [V, V, ctypes.c_int64, V, V]
         L.ccd_batch_indexed.argtypes = [V, P(IndexedDesc), P(ResultSoA), V]
         L.ccd_scene_gamma.argtypes = [V, V, V, ctypes.c_int64, V, V]
+        L.ccd_plan_scratch.argtypes = [P(Tuning), ctypes.c_int, ctypes.c_size_t, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int, P(ScratchPlan)]
         L.ccd_strerror.argtypes = [ctypes.c_int]
         L.ccd_strerror.restype = ctypes.c_char_p
         L.ccd_last_error.argtypes = []
@@ -139,6 +152,20 @@ def _lib():
 def load():
     """Loads the HIP library (raises if it is missing)."""
     return _lib()
+
+
+def plan_scratch(n: int, max_iter: int, num_cu: int = 256, mem_budget_bytes: int = 0,
+                 engine: int = ENGINE_PERSISTENT, **tuning) -> dict:
+    """The scratch plan of a batch (ccd_plan_scratch; host only, no GPU)."""
+    t = Tuning()
+    for k, v in tuning.items():
+        setattr(t, k, int(v))
+    out = ScratchPlan()
+    rc = _lib().ccd_plan_scratch(ctypes.byref(t), int(num_cu), int(mem_budget_bytes), int(n),
+                                 int(max_iter), int(engine), ctypes.byref(out))
+    if rc != OK:
+        raise CCDError(rc, "ccd_plan_scratch")
+    return {f: int(getattr(out, f)) for f, _ in ScratchPlan._fields_}
 
 
 def params(delta=1e-6, max_iter=1_000_000, min_sep=0.0, literal=False, t_max=1.0) -> Params:
@@ -245,7 +272,9 @@ class Context:
         out = {"checks": [[int(s.checks[t][k]) for k in range(2)] for t in range(3)],
                "promoted": [int(s.promoted[0]), int(s.promoted[1])],
                "lane_slots": [int(x) for x in s.lane_slots],
-               "kernel_ms": [float(x) for x in s.kernel_ms], "rc": rc}
+               "kernel_ms": [float(x) for x in s.kernel_ms], "overflowed": int(s.overflowed),
+               "restarted": int(s.restarted), "deep": int(s.deep),
+               "handoff_words": int(s.handoff_words), "rc": rc}
         if rc not in (OK,):
             raise CCDError(rc, "ccd batch counters")
         return out

@@ -30,6 +30,7 @@ constexpr double kCoordLimit = 1e300;
 constexpr uint8_t kStCap = 0x01;
 constexpr uint8_t kStCarry = 0x02;
 constexpr uint8_t kStDepth = 0x04;
+constexpr uint8_t kStOverflow = 0x08;
 constexpr uint8_t kStInvalid = 0x80;
 constexpr uint32_t kFlagLiteral = 0x1u;
 

@@ -401,21 +401,6 @@ __device__ __forceinline__ void kappa_lds(const double* Xs, double kappa[3]) {
     kappa[2] = 3.0 * kv;
 }
 
-// Children of a non-terminal colliding box on the split axis; c1 may be
-// rejected by the prism test of vertex-face queries.
-__device__ __forceinline__ void children(int kind, const State& S, const LevelInfo& L,
-                                         uint64_t bt, uint64_t bu, uint64_t bv, uint64_t c[2][3],
-                                         bool ok[2]) {
-    int d[3] = {S.d[0], S.d[1], S.d[2]};
-    d[L.axis] += 1;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        c[b][0] = bt; c[b][1] = bu; c[b][2] = bv;
-        c[b][L.axis] = 2 * c[b][L.axis] + (uint64_t)b;
-        ok[b] = (kind == kEE) || vf_admit(c[b][1], d[1], c[b][2], d[2]);
-    }
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -623,19 +608,82 @@ __global__ void k_reset(unsigned long long* counters) {
 }
 
 // ---------------------------------------------------------------------------
-// Lane engine.
+// Packed keys.  A level whose total bisection depth D = dt + du + dv is at
+// most 64 stores each box as one u64 key
+//   key = (it << (du + dv)) | (iu << dv) | iv,
+// whose numeric order is the lexicographic (t, u, v) order of Alg. 2.  Every
+// level bisects one axis once, so D is the level number.  Deeper levels store
+// the three indices in three arrays (group engine only).
 
-__device__ __forceinline__ int64_t arena_idx(int K, int b, int i, int j) {
-    return ((int64_t)((b * K + i) * 3 + j)) * 64;
+__device__ __forceinline__ uint64_t shl64(uint64_t x, int s) { return s >= 64 ? 0ull : x << s; }
+__device__ __forceinline__ uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; }
+__device__ __forceinline__ uint64_t mask64(int d) { return d >= 64 ? ~0ull : ((1ull << d) - 1ull); }
+
+struct KeyCodec {
+    int st, su;        // shifts of the t and u fields
+    uint64_t mu, mv;   // masks of the u and v fields
+    __device__ __forceinline__ void init(int du, int dv) {
+        st = du + dv;
+        su = dv;
+        mu = mask64(du);
+        mv = mask64(dv);
+    }
+    __device__ __forceinline__ uint64_t encode(uint64_t t, uint64_t u, uint64_t v) const {
+        return shl64(t, st) | shl64(u, su) | v;
+    }
+    __device__ __forceinline__ void decode(uint64_t k, uint64_t& t, uint64_t& u, uint64_t& v) const {
+        t = shr64(k, st);
+        u = shr64(k, su) & mu;
+        v = k & mv;
+    }
+};
+
+// Child b of a packed key whose split axis field starts at bit sx: the field
+// gains one low bit (0: lower half, 1: upper half), the fields above it move
+// up one bit.  Needs a level number below 64 (the child has depth sum <= 64).
+__device__ __forceinline__ uint64_t child_key(uint64_t key, int sx, uint64_t b) {
+    return shl64(key >> sx, sx + 1) | (b << sx) | (key & mask64(sx));
 }
 
+// Result of a query whose next level does not fit the scratch it was given:
+// Alg. 2's return at the current level's first colliding box f, as at the m_I
+// stop (its t_lo is a lower bound of every root the level's boxes hold, so the
+// value stays conservative), flagged with the overflow status.  Only called
+// after decide() kept the query going, so f exists and the carried box (if
+// any) is later than t_lo(f).
+__device__ __forceinline__ void write_overflow(const BatchArgs& a, int64_t v, const Acc& A,
+                                               const State& S, const LevelInfo& L,
+                                               int64_t max_iter) {
+    Outcome O;
+    O.finish = true;
+    O.toi = L.tmax * ((double)A.ft * L.wt);
+    O.tw = L.tmax * L.wt;
+    const uint64_t n = S.N + S.cnt;
+    O.n = n < (uint64_t)max_iter ? n : (uint64_t)max_iter;
+    O.st = kStOverflow;
+    write_result(a, v, O);
+    atomicAdd(&a.counters[kCntOverflow], 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Lane engine.  One lane owns one query.  Its frontier lives in LDS: two
+// buffers (the level being checked and the next one) of `capacity` packed keys
+// per lane, laid out [buffer][box][thread of the block], so that the 64 lanes
+// of a wavefront touch 64 consecutive words (no bank conflict) whichever box
+// each of them is at.  A query is handed on (a key-format Record) when its
+// next level has more than `capacity` boxes or would need keys wider than 64
+// bits (level 64), or (persistent) once it has used its check budget.
+
 template <bool PERSISTENT>
-__global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
+__global__ __launch_bounds__(kLaneBlock) void k_lane(BatchArgs a, LaneCfg c) {
+    extern __shared__ uint64_t lane_frontier[];
     const int lane = threadIdx.x & 63;
-    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t slot = gtid >> 6;
+    const int64_t gtid = blockIdx.x * (int64_t)kLaneBlock + threadIdx.x;
     const int K = c.capacity;
-    uint64_t* ar = c.arena + slot * (int64_t)(2 * K * 3 * 64) + lane;
+    uint64_t* fr = lane_frontier + threadIdx.x;
+    auto slot = [&](int b, uint32_t i) -> uint64_t& {
+        return fr[((int64_t)b * K + (int64_t)i) * kLaneBlock];
+    };
 
     int64_t q = -1;
     bool fresh = false;
@@ -652,6 +700,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
     State S;
     Acc A;
     LevelInfo L;
+    KeyCodec kc;
     uint32_t idx = 0, next_cnt = 0;
     int cur = 0;
     uint64_t nchk[2] = {0, 0};
@@ -711,6 +760,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 acc_init(A);
                 Q.kappa[0] = Q.kappa[1] = Q.kappa[2] = 0.0;  // set at the level-0 check
                 L = level_info(Q.kappa, S.d, Q.tmax);
+                kc.init(0, 0);
             }
         }
         if (q < 0) continue;
@@ -718,12 +768,9 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
         // ---- one box check (lanes whose level still has boxes)
         if (idx < S.cnt) {
             const bool root = S.level == 0;
-            uint64_t bt = 0, bu = 0, bv = 0;
-            if (!root) {
-                bt = ar[arena_idx(K, cur, idx, 0)];
-                bu = ar[arena_idx(K, cur, idx, 1)];
-                bv = ar[arena_idx(K, cur, idx, 2)];
-            }
+            const uint64_t key = root ? 0ull : slot(cur, idx);
+            uint64_t bt, bu, bv;
+            kc.decode(key, bt, bu, bv);
             // kappa (eq. kappas) comes from the corners of [0,1]^3: the level-0 check
             // produces it when the time interval is the full one
             const bool fused = root && Q.tmax == 1.0;
@@ -742,17 +789,19 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 const bool term = R.small || L.dcap;
                 acc_add(A, bt, bu, bv, term, R.small);
                 if (!term) {
-                    uint64_t ch[2][3];
-                    bool ok[2];
-                    children(Q.kind, S, L, bt, bu, bv, ch, ok);
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        if (!ok[b]) continue;
-                        if (next_cnt < (uint32_t)K) {
-                            ar[arena_idx(K, cur ^ 1, next_cnt, 0)] = ch[b][0];
-                            ar[arena_idx(K, cur ^ 1, next_cnt, 1)] = ch[b][1];
-                            ar[arena_idx(K, cur ^ 1, next_cnt, 2)] = ch[b][2];
-                        }
+                    // both children on the split axis; child 0 keeps the box's
+                    // (u_lo, v_lo), which passed the vertex-face prism test when
+                    // the box was made, so only child 1 is tested
+                    const int ax = L.axis;
+                    const int sx = ax == 0 ? kc.st : (ax == 1 ? kc.su : 0);
+                    const bool ok1 = Q.kind == kEE ||
+                                     vf_admit(ax == 1 ? 2 * bu + 1 : bu, S.d[1] + (ax == 1 ? 1 : 0),
+                                              ax == 2 ? 2 * bv + 1 : bv, S.d[2] + (ax == 2 ? 1 : 0));
+                    const bool fits = S.level < 64;
+                    if (fits && next_cnt < (uint32_t)K) slot(cur ^ 1, next_cnt) = child_key(key, sx, 0);
+                    next_cnt += 1;
+                    if (ok1) {
+                        if (fits && next_cnt < (uint32_t)K) slot(cur ^ 1, next_cnt) = child_key(key, sx, 1);
                         next_cnt += 1;
                     }
                 }
@@ -773,12 +822,12 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
         // ---- end of the level: replay Alg. 2's decisions
         uint64_t rf = 0, rm = 0;
         if (S.level != 0 && need_rank(A, S, Q.literal, Q.max_iter, L)) {
+            const uint64_t fk = kc.encode(A.ft, A.fu, A.fv);
+            const uint64_t mk = kc.encode(A.mt, A.mu, A.mv);
             for (uint32_t i = 0; i < S.cnt; ++i) {
-                const uint64_t kt = ar[arena_idx(K, cur, i, 0)];
-                const uint64_t ku = ar[arena_idx(K, cur, i, 1)];
-                const uint64_t kv = ar[arena_idx(K, cur, i, 2)];
-                rf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
-                rm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
+                const uint64_t k = slot(cur, i);
+                rf += k < fk ? 1 : 0;
+                rm += k < mk ? 1 : 0;
             }
         }
         const Outcome O = decide(A, S, Q.literal, Q.max_iter, L, rf, rm);
@@ -788,8 +837,10 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             continue;
         }
         // hand the query on at the start of a level when the next level does not
-        // fit the lane, or (persistent) when the query has used its budget
-        const bool overflow = next_cnt > (uint32_t)K;
+        // fit the lane (too many boxes, or keys of more than 64 bits), or
+        // (persistent) when the query has used its budget
+        const bool deep = S.level >= 64;
+        const bool overflow = next_cnt > (uint32_t)K || deep;
         bool promote = overflow;
         if (!overflow) {
             advance(S, A, Q.literal, L, next_cnt);
@@ -798,6 +849,7 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
             next_cnt = 0;
             acc_init(A);
             L = level_info(Q.kappa, S.d, Q.tmax);
+            kc.init(S.d[1], S.d[2]);
             promote = PERSISTENT && S.N + S.cnt > c.budget;
         }
         if (promote) {
@@ -808,20 +860,19 @@ __global__ __launch_bounds__(256) void k_lane(BatchArgs a, LaneCfg c) {
                 uint64_t* rec = c.records + (int64_t)r * c.record_words;
                 Record h;
                 h.q = q; h.N = S.N; h.tpend = S.tpend; h.wpend = S.wpend; h.level = S.level;
-                h.d[0] = S.d[0]; h.d[1] = S.d[1]; h.d[2] = S.d[2]; h.cnt = S.cnt; h.pad = 0;
+                h.d[0] = S.d[0]; h.d[1] = S.d[1]; h.d[2] = S.d[2]; h.cnt = S.cnt;
+                h.fmt = kFmtKey;
+                h.words = S.level == 0 ? 0 : S.cnt;
                 *reinterpret_cast<Record*>(rec) = h;
                 uint64_t* boxes = rec + kRecordHeaderWords;
-                for (uint32_t i = 0; i < S.cnt; ++i) {
-                    const bool lvl0 = S.level == 0;
-                    boxes[i] = lvl0 ? 0 : ar[arena_idx(K, cur, i, 0)];
-                    boxes[K + i] = lvl0 ? 0 : ar[arena_idx(K, cur, i, 1)];
-                    boxes[2 * K + i] = lvl0 ? 0 : ar[arena_idx(K, cur, i, 2)];
-                }
+                if (S.level != 0)
+                    for (uint32_t i = 0; i < S.cnt; ++i) boxes[i] = slot(cur, i);
+                if (deep) atomicAdd(&a.counters[kCntDeep], 1ull);
                 q = -1;
             } else if (overflow) {
-                // no record left for a level that does not fit: a capacity the
-                // host guaranteed (one record per query) was exceeded
-                atomicAdd(&a.counters[kCntError], 1ull);
+                // no record left for a level that does not fit (the host provides
+                // one record per query, so this does not happen): flagged return
+                write_overflow(a, q, A, S, L, Q.max_iter);
                 q = -1;
             }
             // else: budget hand-off without a free record; keep solving here
@@ -864,36 +915,6 @@ __device__ __forceinline__ void wave_reduce_acc(Acc& A) {
     }
 }
 
-
-// ---------------------------------------------------------------------------
-// Frontier encodings of the group engine.  A level whose total bisection depth
-// D = dt + du + dv is at most 64 stores each box as one u64 key
-//   key = (it << (du + dv)) | (iu << dv) | iv,
-// whose numeric order is the lexicographic (t, u, v) order of Alg. 2; deeper
-// levels store the three indices in three arrays.
-
-__device__ __forceinline__ uint64_t shl64(uint64_t x, int s) { return s >= 64 ? 0ull : x << s; }
-__device__ __forceinline__ uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; }
-__device__ __forceinline__ uint64_t mask64(int d) { return d >= 64 ? ~0ull : ((1ull << d) - 1ull); }
-
-struct KeyCodec {
-    int st, su;        // shifts of the t and u fields
-    uint64_t mu, mv;   // masks of the u and v fields
-    __device__ __forceinline__ void init(int du, int dv) {
-        st = du + dv;
-        su = dv;
-        mu = mask64(du);
-        mv = mask64(dv);
-    }
-    __device__ __forceinline__ uint64_t encode(uint64_t t, uint64_t u, uint64_t v) const {
-        return shl64(t, st) | shl64(u, su) | v;
-    }
-    __device__ __forceinline__ void decode(uint64_t k, uint64_t& t, uint64_t& u, uint64_t& v) const {
-        t = shr64(k, st);
-        u = shr64(k, su) & mu;
-        v = k & mv;
-    }
-};
 
 // Accumulator of a packed level: keys are single words.
 struct KeyAcc {
@@ -973,10 +994,7 @@ __device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
     K.tm = th ? tm : ~0ull; K.th = th ? 1u : 0u;
 }
 
-// Storage formats of a level in a group arena buffer.
-constexpr int kFmtKey = 0;     // one packed key per box (depth sum <= 64)
-constexpr int kFmtPair = 1;    // one word per sibling pair: parent key | flag << 63
-constexpr int kFmtTriple = 2;  // (it, iu, iv) in three arrays, any depth
+// Pair words (kFmtPair): the flag bit marks a pair whose child 1 passed the prism test.
 constexpr uint64_t kPairFlag = 1ull << 63;  // the pair's child 1 passed the prism test
 
 template <int W>
@@ -989,6 +1007,7 @@ struct GroupShared {
     unsigned long long next_cnt;  // W > 1: words of the next level
     unsigned long long next_box;  // W > 1: boxes of the next level
     int64_t rec;
+    int64_t ho[2];      // hand-off: record index and pool offset (or -1)
     uint64_t cand[64];  // head try: unchecked words below the running first colliding key
 };
 
@@ -1569,7 +1588,8 @@ __device__ __forceinline__ void run_rank(GroupShared<W>& sh, const uint64_t* ct,
 // depth sum allows it, else as triples.
 template <int W, int KIND>
 __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
-                                            uint64_t* base, const Record& h, const double kappa[3],
+                                            uint64_t* base, const Record& h, int fmt, int pa,
+                                            int64_t words, const double kappa[3],
                                             double delta, double min_sep, double tmax,
                                             int64_t max_iter, bool literal, uint64_t& nchk,
                                             uint64_t& slots) {
@@ -1580,9 +1600,6 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
     S.N = h.N; S.tpend = h.tpend; S.wpend = h.wpend; S.level = h.level;
     S.d[0] = h.d[0]; S.d[1] = h.d[1]; S.d[2] = h.d[2]; S.cnt = h.cnt;
     int cur = 0;
-    int fmt = depth_sum(S.d) <= 64 ? kFmtKey : kFmtTriple;
-    int pa = 0;
-    int64_t words = h.cnt;
     while (true) {
         LevelInfo L = level_info(kappa, S.d, tmax);
         // equal in every lane: keep the level's description in scalar registers
@@ -1616,25 +1633,61 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
             return;
         }
         if (nw > (uint64_t)cap) {
-            // the next level does not fit: restart the query in the next engine
+            // The next level does not fit this engine's arena.  Hand the query
+            // on at the start of this level (fully stored in buffer cur): the
+            // next engine checks the level again and goes on from there.  Its
+            // boxes go to the hand-off pool; when the pool is full the record
+            // restarts the query at level 0 instead (same results, more work).
+            // With no next engine (or no record left) the query ends here with
+            // the flagged overflow return.
+            const int64_t nwords = (fmt == kFmtTriple ? 3 : 1) * words;
             if (tid == 0) {
-                bool placed = false;
+                int64_t o = -1, p = -1;
                 if (g.out_records) {
-                    const unsigned long long o = atomicAdd(&a.counters[g.out_count_idx], 1ull);
-                    if ((int64_t)o < g.out_record_cap) {
-                        uint64_t* orec = g.out_records + (int64_t)o * g.out_record_words;
-                        Record nh;
-                        nh.q = h.q; nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
-                        nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.pad = 0;
-                        *reinterpret_cast<Record*>(orec) = nh;
-                        const int64_t ok = (g.out_record_words - kRecordHeaderWords) / 3;
-                        orec[kRecordHeaderWords] = 0;
-                        orec[kRecordHeaderWords + ok] = 0;
-                        orec[kRecordHeaderWords + 2 * ok] = 0;
-                        placed = true;
+                    const unsigned long long r = atomicAdd(&a.counters[g.out_count_idx], 1ull);
+                    if ((int64_t)r < g.out_record_cap) {
+                        o = (int64_t)r;
+                        const unsigned long long po =
+                            atomicAdd(&a.counters[kCntPool], (unsigned long long)nwords);
+                        if ((int64_t)po + nwords <= g.out_pool_words) p = (int64_t)po;
                     }
                 }
-                if (!placed) atomicAdd(&a.counters[kCntError], 1ull);
+                sh.ho[0] = o;
+                sh.ho[1] = p;
+            }
+            __syncthreads();
+            const int64_t o = uni64s(sh.ho[0]), p = uni64s(sh.ho[1]);
+            if (o < 0) {
+                if (tid == 0) write_overflow(a, h.q, A, S, L, max_iter);
+                return;
+            }
+            uint64_t* orec = g.out_records + o * g.out_record_words;
+            if (p >= 0) {
+                uint64_t* dst = g.out_pool + p;
+                for (int64_t i = tid; i < words; i += T) {
+                    dst[i] = ct[i];
+                    if (fmt == kFmtTriple) {
+                        dst[words + i] = ct[cap + i];
+                        dst[2 * words + i] = ct[2 * cap + i];
+                    }
+                }
+            }
+            if (tid == 0) {
+                Record nh;
+                nh.q = h.q;
+                if (p >= 0) {
+                    nh.N = S.N; nh.tpend = S.tpend; nh.wpend = S.wpend; nh.level = S.level;
+                    nh.d[0] = S.d[0]; nh.d[1] = S.d[1]; nh.d[2] = S.d[2]; nh.cnt = S.cnt;
+                    nh.fmt = (uint32_t)fmt | ((uint32_t)pa << 4);
+                    nh.words = (uint64_t)words;
+                    orec[kRecordHeaderWords] = (uint64_t)p;
+                } else {
+                    nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
+                    nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.fmt = kFmtKey; nh.words = 0;
+                    orec[kRecordHeaderWords] = 0;
+                    atomicAdd(&a.counters[kCntRestart], 1ull);
+                }
+                *reinterpret_cast<Record*>(orec) = nh;
             }
             return;
         }
@@ -1673,7 +1726,6 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
     uint64_t* base = g.arena + (int64_t)blockIdx.x * (6 * cap);
     int64_t in_count = (int64_t)__atomic_load_n(&a.counters[g.in_count_idx], __ATOMIC_RELAXED);
     if (in_count > g.in_record_cap) in_count = g.in_record_cap;
-    const int64_t in_k = (g.in_record_words - kRecordHeaderWords) / 3;
     uint64_t nchk[2] = {0, 0};
     uint64_t slots = 0;
     while (true) {
@@ -1703,18 +1755,35 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
             const int c = tid % 3, k = tid / 3;
             sh.Xs[c * 8 + k] = qv.pos[(int64_t)tid * qv.n + q];
         }
-        const uint64_t* rb = rec + kRecordHeaderWords;
-        if (depth_sum(h.d) <= 64) {
+        h.fmt = uni32(h.fmt);
+        h.words = uni64(h.words);
+        // the record's level into buffer 0 of the arena: keys and pairs as they
+        // are, triples packed into keys when the depth sum allows it; a level-0
+        // record is the root box alone
+        int fmt = (int)(h.fmt & 3u), pa = (int)((h.fmt >> 4) & 3u);
+        int64_t words = (int64_t)h.words;
+        const uint64_t* rb = g.in_pool ? g.in_pool + rec[kRecordHeaderWords] : rec + kRecordHeaderWords;
+        if (h.level == 0 || words > cap || fmt > kFmtTriple) {
+            // (words > cap and unknown formats cannot come from the engines
+            // before this one; restarting from the root is always correct)
+            h.N = 0; h.tpend = INFINITY; h.wpend = 0.0; h.level = 0;
+            h.d[0] = h.d[1] = h.d[2] = 0; h.cnt = 1;
+            fmt = kFmtKey; pa = 0; words = 1;
+            if (tid == 0) base[0] = 0;
+        } else if (fmt == kFmtTriple && depth_sum(h.d) <= 64) {
             KeyCodec kc;
             kc.init(h.d[1], h.d[2]);
-            for (int64_t i = tid; i < (int64_t)h.cnt; i += T)
-                base[i] = kc.encode(rb[i], rb[in_k + i], rb[2 * in_k + i]);
-        } else {
-            for (int64_t i = tid; i < (int64_t)h.cnt; i += T) {
+            for (int64_t i = tid; i < words; i += T)
+                base[i] = kc.encode(rb[i], rb[words + i], rb[2 * words + i]);
+            fmt = kFmtKey;
+        } else if (fmt == kFmtTriple) {
+            for (int64_t i = tid; i < words; i += T) {
                 base[i] = rb[i];
-                base[cap + i] = rb[in_k + i];
-                base[2 * cap + i] = rb[2 * in_k + i];
+                base[cap + i] = rb[words + i];
+                base[2 * cap + i] = rb[2 * words + i];
             }
+        } else {
+            for (int64_t i = tid; i < words; i += T) base[i] = rb[i];
         }
         __syncthreads();
         if (tid < 3) {
@@ -1731,11 +1800,11 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         for (int k = 0; k < 3; ++k) kappa[k] = unif64(kappa[k]);
         __syncthreads();
         if (kind == kEE)
-            group_query<W, kEE>(a, g, sh, base, h, kappa, delta, min_sep, tmax, max_iter, literal,
-                               nchk[1], slots);
+            group_query<W, kEE>(a, g, sh, base, h, fmt, pa, words, kappa, delta, min_sep, tmax,
+                                max_iter, literal, nchk[1], slots);
         else
-            group_query<W, kVF>(a, g, sh, base, h, kappa, delta, min_sep, tmax, max_iter, literal,
-                               nchk[0], slots);
+            group_query<W, kVF>(a, g, sh, base, h, fmt, pa, words, kappa, delta, min_sep, tmax,
+                                max_iter, literal, nchk[0], slots);
         __syncthreads();
     }
     if (tid == 0) {

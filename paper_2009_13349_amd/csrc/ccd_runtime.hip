@@ -85,7 +85,7 @@ struct ccd_context {
     size_t budget = 0;
     int engine = CCD_ENGINE_PERSISTENT;
     ccd_tuning tune{};
-    DevBuf counters, order, lane_arena, rec_a, group_arena, rec_b, block_arena;
+    DevBuf counters, order, rec_a, group_arena, rec_b, pool, block_arena;
     DevBuf io;      // staging for host-pointer batches
     DevBuf gather;  // structure-of-arrays coordinates of an indexed batch
     bool timing = false;
@@ -118,11 +118,13 @@ void default_tuning(ccd_tuning& t, int num_cu) {
     t.group_capacity = 1 << 16;
     t.block_count = num_cu;
     t.group_occupancy = 3;
+    t.block_capacity = 0;             // 2 m_I + 2, within the budget
+    t.handoff_words = int64_t(1) << 25;  // 256 MiB
 }
 
 void clamp_tuning(ccd_tuning& t) {
     t.lane_waves_per_cu = std::min(32, std::max(1, t.lane_waves_per_cu));
-    t.lane_capacity = std::min(256, std::max(8, t.lane_capacity));
+    t.lane_capacity = std::min(32, std::max(8, t.lane_capacity));
     t.lane_budget = std::max<int64_t>(1, t.lane_budget);
     if (t.group_waves >= 8) t.group_waves = 8;
     else if (t.group_waves >= 4) t.group_waves = 4;
@@ -132,6 +134,8 @@ void clamp_tuning(ccd_tuning& t) {
     t.group_capacity = std::min<int64_t>(int64_t(1) << 28, std::max<int64_t>(256, t.group_capacity));
     t.block_count = std::min(1 << 12, std::max(1, t.block_count));
     t.group_occupancy = std::min(4, std::max(1, t.group_occupancy));
+    t.block_capacity = t.block_capacity <= 0 ? 0 : std::max<int64_t>(256, t.block_capacity);
+    t.handoff_words = std::min<int64_t>(int64_t(1) << 34, std::max<int64_t>(0, t.handoff_words));
 }
 
 // 0 < t_max <= 1 (false for NaN), no unknown flags.
@@ -160,111 +164,177 @@ bool host_query_valid(const double X[24], int kind, double delta, int64_t max_it
 struct Plan {
     int64_t n;
     int lane_slots;
-    int lane_grid;       // blocks of 256 threads
+    int lane_grid;       // blocks of kLaneBlock threads
+    size_t lane_lds;     // dynamic LDS bytes per lane-engine block
     int64_t rec_a_words, rec_a_cap;
     int64_t rec_b_words, rec_b_cap;
+    int64_t pool_words;  // group -> block hand-off pool
     int group_count;
     int64_t group_cap;
     int block_count;
     int64_t block_cap;
 };
 
-int make_plan(ccd_context* ctx, int64_t n, int64_t max_iter_max, bool persistent, Plan& P) {
-    const ccd_tuning& t = ctx->tune;
+// Saturating size arithmetic: a result that does not fit size_t becomes
+// SIZE_MAX, which no budget admits.
+size_t smul(size_t a, size_t b) {
+    size_t r;
+    return __builtin_mul_overflow(a, b, &r) ? SIZE_MAX : r;
+}
+size_t sadd(size_t a, size_t b) {
+    size_t r;
+    return __builtin_add_overflow(a, b, &r) ? SIZE_MAX : r;
+}
+
+constexpr size_t kArenaBytesPerWord = 6 * 8;  // two buffers of up to three words per box
+
+// Sizes the scratch of a launch of n queries whose largest m_I is max_iter_max
+// within the context's budget.  The block engine's arena would need 2 m_I + 2
+// words per buffer for every query to finish there (a level of a query that
+// has not returned has fewer than 2 m_I boxes); it is clamped to a quarter of
+// the budget (and to the tuning's block_capacity), and a query whose level
+// outgrows it ends with the flagged overflow return.
+int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t max_iter_max,
+             bool persistent, Plan& P) {
+    std::memset(&P, 0, sizeof(P));  // padding too: plans are compared bytewise (graph reuse)
     P.n = n;
     const int K = t.lane_capacity;
     if (persistent) {
-        P.lane_slots = ctx->num_cu * t.lane_waves_per_cu;
-        P.lane_grid = (P.lane_slots * 64 + 255) / 256;
-        P.lane_slots = P.lane_grid * 4;
+        const int64_t threads = (int64_t)num_cu * t.lane_waves_per_cu * 64;
+        P.lane_grid = (int)((threads + kLaneBlock - 1) / kLaneBlock);
     } else {
-        P.lane_grid = (int)((n + 255) / 256);
-        P.lane_slots = P.lane_grid * 4;
+        P.lane_grid = (int)((n + kLaneBlock - 1) / kLaneBlock);
     }
-    P.rec_a_words = kRecordHeaderWords + 3 * (int64_t)K;
+    P.lane_slots = P.lane_grid * (kLaneBlock / 64);
+    P.lane_lds = (size_t)2 * K * kLaneBlock * 8;
+    P.rec_a_words = kRecordHeaderWords + (int64_t)K;
     P.rec_a_cap = n;
-    P.rec_b_words = kRecordHeaderWords + 3;
+    P.rec_b_words = kRecordHeaderWords + 1;
     P.rec_b_cap = n;
     P.group_cap = std::max<int64_t>(t.group_capacity, K);
     P.group_count = t.group_count;
-    // the widest frontier a level can reach before Alg. 2 stops is < 2 m_I
-    P.block_cap = std::max<int64_t>(2 * max_iter_max + 2, 64);
     P.block_count = t.block_count;
 
-    const size_t fixed = 64 * 8 + (size_t)n * 8                                // counters, order
-                         + (size_t)P.lane_slots * 2 * K * 3 * 64 * 8           // lane arenas
-                         + (size_t)P.rec_a_cap * P.rec_a_words * 8             // records A
-                         + (size_t)P.rec_b_cap * P.rec_b_words * 8;            // records B
-    const size_t per_group = (size_t)6 * P.group_cap * 8;
-    const size_t per_block = (size_t)6 * P.block_cap * 8;
-    if (fixed + per_group + per_block > ctx->budget) return CCD_ENOMEM;
-    size_t left = ctx->budget - fixed;
-    // the group engine carries the bulk of the work: it gets up to 3/4 of what is
-    // left after one block arena; the block engine (rarely used) gets the rest
-    size_t groups_fit = std::max<size_t>(1, ((left - per_block) / 4 * 3) / per_group);
-    P.group_count = (int)std::min<size_t>(P.group_count, groups_fit);
-    left -= (size_t)P.group_count * per_group;
-    size_t blocks_fit = std::max<size_t>(1, left / per_block);
-    P.block_count = (int)std::min<size_t>(P.block_count, blocks_fit);
+    const size_t fixed = sadd(sadd(sadd(64 * 8, smul((size_t)n, 8)),                        // counters, order
+                                   smul(smul((size_t)P.rec_a_cap, (size_t)P.rec_a_words), 8)),  // records A
+                              smul(smul((size_t)P.rec_b_cap, (size_t)P.rec_b_words), 8));       // records B
+    const size_t per_group = smul((size_t)P.group_cap, kArenaBytesPerWord);
+    // the block engine takes the group engine's hand-offs, so its arena is at
+    // least a group arena
+    const size_t min_block = per_group;
+    if (sadd(sadd(fixed, per_group), min_block) > budget) {
+        set_last_error("scratch plan: device memory budget too small for the batch");
+        return CCD_ENOMEM;
+    }
+    size_t left = budget - fixed;
+    // block arena capacity: min(2 m_I + 2, tuning, a quarter of what is left)
+    uint64_t want = max_iter_max >= (INT64_MAX - 2) / 2 ? (uint64_t)INT64_MAX
+                                                        : (uint64_t)(2 * max_iter_max + 2);
+    if (t.block_capacity > 0) want = std::min<uint64_t>(want, (uint64_t)t.block_capacity);
+    const uint64_t quarter = (uint64_t)(left / 4 / kArenaBytesPerWord);
+    want = std::min<uint64_t>(want, quarter);
+    P.block_cap = (int64_t)std::max<uint64_t>(want, (uint64_t)P.group_cap);
+    const size_t per_block = smul((size_t)P.block_cap, kArenaBytesPerWord);
+    left -= per_block;  // one block arena always (<= left: quarter or per_group checked above)
+    // hand-off pool: the tuning's size, at most an eighth of what is left
+    P.pool_words = std::min<int64_t>(t.handoff_words, (int64_t)(left / 8 / 8));
+    left -= (size_t)P.pool_words * 8;
+    // the group engine carries the bulk of the work: it gets up to 3/4 of what
+    // is left; further blocks (rarely used) get the rest
+    const size_t groups_fit = std::max<size_t>(1, (left / 4 * 3) / per_group);
+    P.group_count = (int)std::min<size_t>((size_t)P.group_count, groups_fit);
+    left -= std::min(left, (size_t)P.group_count * per_group);
+    const size_t blocks_fit = 1 + left / per_block;
+    P.block_count = (int)std::min<size_t>((size_t)P.block_count, blocks_fit);
     return CCD_OK;
 }
 
+int make_plan(ccd_context* ctx, int64_t n, int64_t max_iter_max, bool persistent, Plan& P) {
+    return plan_for(ctx->tune, ctx->num_cu, ctx->budget, n, max_iter_max, persistent, P);
+}
+
+size_t plan_bytes(const Plan& P) {
+    return 64 * 8 + (size_t)P.n * 8 + (size_t)P.rec_a_cap * P.rec_a_words * 8 +
+           (size_t)P.rec_b_cap * P.rec_b_words * 8 + (size_t)P.pool_words * 8 +
+           (size_t)P.group_count * P.group_cap * kArenaBytesPerWord +
+           (size_t)P.block_count * P.block_cap * kArenaBytesPerWord;
+}
+
 int ensure_scratch(ccd_context* ctx, const Plan& P) {
-    const int K = ctx->tune.lane_capacity;
     bool ok = grow(ctx->counters, 64 * 8) && grow(ctx->order, (size_t)P.n * 8) &&
-              grow(ctx->lane_arena, (size_t)P.lane_slots * 2 * K * 3 * 64 * 8) &&
               grow(ctx->rec_a, (size_t)P.rec_a_cap * P.rec_a_words * 8) &&
               grow(ctx->rec_b, (size_t)P.rec_b_cap * P.rec_b_words * 8) &&
-              grow(ctx->group_arena, (size_t)P.group_count * 6 * P.group_cap * 8) &&
-              grow(ctx->block_arena, (size_t)P.block_count * 6 * P.block_cap * 8);
+              grow(ctx->pool, (size_t)P.pool_words * 8) &&
+              grow(ctx->group_arena, (size_t)P.group_count * P.group_cap * kArenaBytesPerWord) &&
+              grow(ctx->block_arena, (size_t)P.block_count * P.block_cap * kArenaBytesPerWord);
     return ok ? CCD_OK : CCD_ENOMEM;
 }
 
-// Issues the batch's kernel sequence on stream s.
-void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool persistent,
-             bool timed) {
-    const int K = ctx->tune.lane_capacity;
-    a.counters = (unsigned long long*)ctx->counters.p;
+// Device scratch of one launch (the context's buffers, or the carved static
+// array of the allocation-free entry point).
+struct Scratch {
+    unsigned long long* counters;
+    int64_t* order;
+    uint64_t* rec_a;
+    uint64_t* rec_b;
+    uint64_t* pool;
+    uint64_t* group_arena;
+    uint64_t* block_arena;
+};
+
+Scratch context_scratch(ccd_context* ctx) {
+    return Scratch{(unsigned long long*)ctx->counters.p, (int64_t*)ctx->order.p,
+                   (uint64_t*)ctx->rec_a.p, (uint64_t*)ctx->rec_b.p, (uint64_t*)ctx->pool.p,
+                   (uint64_t*)ctx->group_arena.p, (uint64_t*)ctx->block_arena.p};
+}
+
+// Issues the batch's kernel sequence on stream s (events ev[0..4] between the
+// kernels when timed).
+void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs a, hipStream_t s,
+             bool persistent, bool timed, hipEvent_t* ev) {
+    const int K = tune.lane_capacity;
+    a.counters = X.counters;
     a.order = nullptr;
-    if (timed) (void)hipEventRecord(ctx->ev[0], s);
+    if (timed) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.counters);
     if (persistent) {
         // level 0 of every query; the survivors, grouped by kind, go on
-        hipLaunchKernelGGL(k_root, dim3((unsigned)((P.n + 511) / 512)), dim3(512), 0, s, a,
-                           (int64_t*)ctx->order.p);
-        a.order = (const int64_t*)ctx->order.p;
+        hipLaunchKernelGGL(k_root, dim3((unsigned)((P.n + 511) / 512)), dim3(512), 0, s, a, X.order);
+        a.order = X.order;
     }
-    if (timed) (void)hipEventRecord(ctx->ev[1], s);
+    if (timed) (void)hipEventRecord(ev[1], s);
     LaneCfg lc;
     lc.capacity = K;
     lc.persistent = persistent ? 1 : 0;
     lc.survivors = persistent ? 1 : 0;
     lc.pad = 0;
-    lc.budget = persistent ? (uint64_t)ctx->tune.lane_budget : ~0ull;
-    lc.arena = (uint64_t*)ctx->lane_arena.p;
-    lc.records = (uint64_t*)ctx->rec_a.p;
+    lc.budget = persistent ? (uint64_t)tune.lane_budget : ~0ull;
+    lc.records = X.rec_a;
     lc.record_words = P.rec_a_words;
     lc.record_cap = P.rec_a_cap;
     if (persistent)
-        hipLaunchKernelGGL(k_lane<true>, dim3(P.lane_grid), dim3(256), 0, s, a, lc);
+        hipLaunchKernelGGL(k_lane<true>, dim3(P.lane_grid), dim3(kLaneBlock), P.lane_lds, s, a, lc);
     else
-        hipLaunchKernelGGL(k_lane<false>, dim3(P.lane_grid), dim3(256), 0, s, a, lc);
-    if (timed) (void)hipEventRecord(ctx->ev[2], s);
+        hipLaunchKernelGGL(k_lane<false>, dim3(P.lane_grid), dim3(kLaneBlock), P.lane_lds, s, a, lc);
+    if (timed) (void)hipEventRecord(ev[2], s);
 
     GroupCfg g;
     g.capacity = P.group_cap;
-    g.arena = (uint64_t*)ctx->group_arena.p;
-    g.in_records = (const uint64_t*)ctx->rec_a.p;
+    g.arena = X.group_arena;
+    g.in_records = X.rec_a;
     g.in_record_words = P.rec_a_words;
     g.in_record_cap = P.rec_a_cap;
+    g.in_pool = nullptr;
     g.in_count_idx = kCntRecA;
     g.in_take_idx = kCntRecATake;
-    g.out_records = (uint64_t*)ctx->rec_b.p;
+    g.out_records = X.rec_b;
     g.out_record_words = P.rec_b_words;
     g.out_record_cap = P.rec_b_cap;
+    g.out_pool = X.pool;
+    g.out_pool_words = P.pool_words;
     g.out_count_idx = kCntRecB;
     g.tier = 1;
-    switch (ctx->tune.group_waves) {
+    switch (tune.group_waves) {
         case 8:
             hipLaunchKernelGGL((k_group<8, 1>), dim3(P.group_count), dim3(512), 0, s, a, g);
             break;
@@ -275,7 +345,7 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
             hipLaunchKernelGGL((k_group<4, 1>), dim3(P.group_count), dim3(256), 0, s, a, g);
             break;
         default:
-            switch (ctx->tune.group_occupancy) {
+            switch (tune.group_occupancy) {
                 case 4:
                     hipLaunchKernelGGL((k_group<1, 4>), dim3(P.group_count), dim3(64), 0, s, a, g);
                     break;
@@ -289,23 +359,26 @@ void enqueue(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool p
                     hipLaunchKernelGGL((k_group<1, 1>), dim3(P.group_count), dim3(64), 0, s, a, g);
             }
     }
-    if (timed) (void)hipEventRecord(ctx->ev[3], s);
+    if (timed) (void)hipEventRecord(ev[3], s);
 
     GroupCfg b;
     b.capacity = P.block_cap;
-    b.arena = (uint64_t*)ctx->block_arena.p;
-    b.in_records = (const uint64_t*)ctx->rec_b.p;
+    b.arena = X.block_arena;
+    b.in_records = X.rec_b;
     b.in_record_words = P.rec_b_words;
     b.in_record_cap = P.rec_b_cap;
+    b.in_pool = X.pool;
     b.in_count_idx = kCntRecB;
     b.in_take_idx = kCntRecBTake;
     b.out_records = nullptr;
     b.out_record_words = 0;
     b.out_record_cap = 0;
+    b.out_pool = nullptr;
+    b.out_pool_words = 0;
     b.out_count_idx = 0;
     b.tier = 2;
     hipLaunchKernelGGL((k_group<8, 1>), dim3(P.block_count), dim3(512), 0, s, a, b);
-    if (timed) (void)hipEventRecord(ctx->ev[4], s);
+    if (timed) (void)hipEventRecord(ev[4], s);
 }
 
 // Everything the launch sequence depends on; a graph is reused while this is
@@ -337,8 +410,8 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
         key.a = a;
         key.P = P;
         key.tune = ctx->tune;
-        void* bufs[7] = {ctx->counters.p, ctx->order.p, ctx->lane_arena.p, ctx->rec_a.p,
-                         ctx->group_arena.p, ctx->rec_b.p, ctx->block_arena.p};
+        void* bufs[7] = {ctx->counters.p, ctx->order.p, ctx->rec_a.p, ctx->group_arena.p,
+                         ctx->rec_b.p, ctx->pool.p, ctx->block_arena.p};
         std::memcpy(key.bufs, bufs, sizeof(bufs));
         key.persistent = persistent;
         key.timed = timed;
@@ -350,7 +423,8 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
             bool ok = hip_ok(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
                              "hipStreamBeginCapture");
             if (ok) {
-                enqueue(ctx, P, a, ctx->cap_stream, persistent, timed);
+                enqueue(ctx->tune, P, context_scratch(ctx), a, ctx->cap_stream, persistent, timed,
+                        ctx->ev);
                 hipGraph_t g = nullptr;
                 ok = hip_ok(hipStreamEndCapture(ctx->cap_stream, &g), "hipStreamEndCapture");
                 if (ok) {
@@ -371,7 +445,7 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
         }
         return hip_ok(hipGraphLaunch(ctx->graph_exec, s), "hipGraphLaunch") ? CCD_OK : CCD_EDEVICE;
     }
-    enqueue(ctx, P, a, s, persistent, timed);
+    enqueue(ctx->tune, P, context_scratch(ctx), a, s, persistent, timed, ctx->ev);
     return hip_ok(hipGetLastError(), "kernel launch") ? CCD_OK : CCD_EDEVICE;
 }
 
@@ -509,14 +583,55 @@ void ccd_context_destroy(ccd_context* c) {
     if (!c) return;
     (void)set_device(c->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&c->counters, &c->order, &c->lane_arena, &c->rec_a, &c->group_arena,
-                      &c->rec_b, &c->block_arena, &c->io, &c->gather})
+    for (DevBuf* b : {&c->counters, &c->order, &c->rec_a, &c->group_arena, &c->rec_b, &c->pool,
+                      &c->block_arena, &c->io, &c->gather})
         release(*b);
     if (c->have_events)
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
+}
+
+int ccd_plan_scratch(const ccd_tuning* tuning, int num_cu, size_t mem_budget_bytes, int64_t n,
+                     int64_t max_iter, int engine, ccd_scratch_plan* out) {
+    if (!out || num_cu < 1 || n < 0 || max_iter < 1 ||
+        (engine != CCD_ENGINE_PERSISTENT && engine != CCD_ENGINE_PLAIN)) {
+        set_last_error("ccd_plan_scratch: bad argument");
+        return CCD_EINVAL;
+    }
+    ccd_tuning t;
+    default_tuning(t, num_cu);
+    if (tuning) {
+        ccd_tuning n2 = t;
+        const ccd_tuning* u = tuning;
+        if (u->lane_waves_per_cu) n2.lane_waves_per_cu = u->lane_waves_per_cu;
+        if (u->lane_capacity) n2.lane_capacity = u->lane_capacity;
+        if (u->lane_budget) n2.lane_budget = u->lane_budget;
+        if (u->group_waves) n2.group_waves = u->group_waves;
+        if (u->group_count) n2.group_count = u->group_count;
+        if (u->group_capacity) n2.group_capacity = u->group_capacity;
+        if (u->block_count) n2.block_count = u->block_count;
+        if (u->group_occupancy) n2.group_occupancy = u->group_occupancy;
+        if (u->block_capacity) n2.block_capacity = u->block_capacity < 0 ? 0 : u->block_capacity;
+        if (u->handoff_words) n2.handoff_words = u->handoff_words < 0 ? 0 : u->handoff_words;
+        clamp_tuning(n2);
+        t = n2;
+    }
+    Plan P;
+    const size_t budget = mem_budget_bytes ? mem_budget_bytes : ((size_t)16 << 30);
+    const int rc = plan_for(t, num_cu, budget, n, max_iter, engine == CCD_ENGINE_PERSISTENT, P);
+    if (rc != CCD_OK) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->bytes = plan_bytes(P);
+    out->lane_lds_bytes = P.lane_lds;
+    out->lane_blocks = P.lane_grid;
+    out->group_count = P.group_count;
+    out->group_capacity = P.group_cap;
+    out->block_count = P.block_count;
+    out->block_capacity = P.block_cap;
+    out->handoff_words = P.pool_words;
+    return CCD_OK;
 }
 
 int ccd_context_set_engine(ccd_context* c, int engine) {
@@ -542,6 +657,8 @@ int ccd_context_set_tuning(ccd_context* c, const ccd_tuning* t) {
     if (t->group_capacity) n.group_capacity = t->group_capacity;
     if (t->block_count) n.block_count = t->block_count;
     if (t->group_occupancy) n.group_occupancy = t->group_occupancy;
+    if (t->block_capacity) n.block_capacity = t->block_capacity < 0 ? 0 : t->block_capacity;
+    if (t->handoff_words) n.handoff_words = t->handoff_words < 0 ? 0 : t->handoff_words;
     clamp_tuning(n);
     c->tune = n;
     return CCD_OK;
@@ -581,12 +698,15 @@ int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
     out->promoted[0] = h[kCntRecA];
     out->promoted[1] = h[kCntRecB];
     for (int t = 0; t < 3; ++t) out->lane_slots[t] = h[kCntSlots + t];
+    out->overflowed = h[kCntOverflow];
+    out->restarted = h[kCntRestart];
+    out->deep = h[kCntDeep];
+    out->handoff_words = h[kCntPool];
     if (c->last_timed)
         for (int i = 0; i < 4; ++i)
             if (!hip_ok(hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]),
                         "hipEventElapsedTime"))
                 out->kernel_ms[i] = 0.0f;
-    if (h[kCntError]) return CCD_ENOMEM;
     return CCD_OK;
 }
 
@@ -676,21 +796,13 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
         a.status = (uint8_t*)(base + o_st);
         int rc = ccd::run_args(ctx, a, mi_max, s);
         if (rc != CCD_OK) return rc;
-        unsigned long long err = 0;
         ok = hip_ok(hipMemcpyAsync(out->toi, a.toi, n * 8, hipMemcpyDeviceToHost, s), "copy toi") &&
              hip_ok(hipMemcpyAsync(out->t_width, a.t_width, n * 8, hipMemcpyDeviceToHost, s), "copy t_width") &&
              hip_ok(hipMemcpyAsync(out->hit, a.hit, n, hipMemcpyDeviceToHost, s), "copy hit") &&
              hip_ok(hipMemcpyAsync(out->n_checks, a.n_checks, n * 8, hipMemcpyDeviceToHost, s), "copy n_checks") &&
              hip_ok(hipMemcpyAsync(out->status, a.status, n, hipMemcpyDeviceToHost, s), "copy status") &&
-             hip_ok(hipMemcpyAsync(&err, (unsigned long long*)ctx->counters.p + kCntError, 8,
-                                   hipMemcpyDeviceToHost, s), "copy error counter") &&
              hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (!ok) return CCD_EDEVICE;
-        if (err) {
-            std::snprintf(g_last_error, sizeof(g_last_error), "scratch capacity exceeded");
-            return CCD_ENOMEM;
-        }
-        return CCD_OK;
+        return ok ? CCD_OK : CCD_EDEVICE;
     }
 
     // device pointers: per-query m_I must be known on the host to size the
@@ -772,7 +884,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
     const std::vector<Knob> knobs = {
         {0, {2, 3, 4}},            // group_occupancy (with group_count = 4 * cu * occ)
         {1, {32, 64, 128, 192, 256, 384, 512}},  // lane_budget
-        {2, {16, 32, 64}},         // lane_capacity
+        {2, {8, 16, 32}},          // lane_capacity
         {3, {4, 8, 12}},           // lane_waves_per_cu
         {4, {1, 2}},               // group_waves
     };
@@ -831,7 +943,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
 }
 
 // Tuning cache: one line per (device, workload key):
-//   <arch> <cus> <hip-version> <key> <the eight ccd_tuning fields>
+//   <arch> <cus> <hip-version> <key> <the ten ccd_tuning fields>
 namespace {
 void device_tag(ccd_context* ctx, char* arch, size_t n, int* hipver) {
     hipDeviceProp_t prop;
@@ -868,9 +980,10 @@ int ccd_tuning_cache_store(ccd_context* ctx, const char* path, const char* key) 
     if (!f) return CCD_EINVAL;
     for (const std::string& l : keep) std::fputs(l.c_str(), f);
     const ccd_tuning& t = ctx->tune;
-    std::fprintf(f, "%s %d %d %s %d %d %lld %d %d %lld %d %d\n", arch, ctx->num_cu, ver, key,
-                 t.lane_waves_per_cu, t.lane_capacity, (long long)t.lane_budget, t.group_waves,
-                 t.group_count, (long long)t.group_capacity, t.block_count, t.group_occupancy);
+    std::fprintf(f, "%s %d %d %s %d %d %lld %d %d %lld %d %d %lld %lld\n", arch, ctx->num_cu, ver,
+                 key, t.lane_waves_per_cu, t.lane_capacity, (long long)t.lane_budget, t.group_waves,
+                 t.group_count, (long long)t.group_capacity, t.block_count, t.group_occupancy,
+                 (long long)t.block_capacity, (long long)t.handoff_words);
     std::fclose(f);
     return CCD_OK;
 }
@@ -888,14 +1001,16 @@ int ccd_tuning_cache_load(ccd_context* ctx, const char* path, const char* key) {
     while (std::fgets(line, sizeof(line), f)) {
         char a[128], k[128];
         int c, v;
-        long long lb, gc;
+        long long lb, gc, bc, hw;
         ccd_tuning r{};
-        if (std::sscanf(line, "%127s %d %d %127s %d %d %lld %d %d %lld %d %d", a, &c, &v, k,
+        if (std::sscanf(line, "%127s %d %d %127s %d %d %lld %d %d %lld %d %d %lld %lld", a, &c, &v, k,
                         &r.lane_waves_per_cu, &r.lane_capacity, &lb, &r.group_waves, &r.group_count,
-                        &gc, &r.block_count, &r.group_occupancy) == 12 &&
+                        &gc, &r.block_count, &r.group_occupancy, &bc, &hw) == 14 &&
             std::strcmp(a, arch) == 0 && c == ctx->num_cu && v == ver && std::strcmp(k, key) == 0) {
             r.lane_budget = lb;
             r.group_capacity = gc;
+            r.block_capacity = bc;
+            r.handoff_words = hw;
             t = r;
             found = 1;
         }

@@ -68,7 +68,7 @@ def test_struct_layouts_match_header(tmp_path):
                "ccd_batch_desc": ccd.BatchDesc, "ccd_result_soa": ccd.ResultSoA,
                "ccd_stats": ccd.Stats, "ccd_indexed_desc": ccd.IndexedDesc,
                "ccd_serve_config": ccd.ServeConfig, "ccd_serve_info": ccd.ServeInfo,
-               "ccd_serve_stats": ccd.ServeStats}
+               "ccd_serve_stats": ccd.ServeStats, "ccd_scratch_plan": ccd.ScratchPlan}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ccd.h"', "int main(void) {"]
     for cname, cls in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -94,3 +94,39 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.ccd_batch(None, None, None, None) == ccd.EINVAL
     assert lib.ccd_context_set_engine(None, 0) == ccd.EINVAL
     assert lib.ccd_vf(None, None, None, None) == ccd.EINVAL
+
+
+def test_scratch_plan_sizes_are_overflow_safe(lib):
+    """The scratch plan (host-only) stays inside the budget for any m_I: the
+    block engine's arena is 2 m_I + 2 words per buffer clamped to a quarter of
+    the budget, computed without wrapping at m_I = 1e18 or INT64_MAX."""
+    from paper_2009_13349_amd import ccd
+    budget = 32 << 30
+    small = ccd.plan_scratch(1_000_000, 1_000_000, mem_budget_bytes=budget)
+    assert small["block_capacity"] == 2 * 1_000_000 + 2
+    assert small["bytes"] <= budget
+    for mi in (10 ** 18, 2 ** 63 - 1, 2 ** 62, 190_000_000_000_000_000):
+        p = ccd.plan_scratch(1_000_000, mi, mem_budget_bytes=budget)
+        assert p["bytes"] <= budget, (mi, p)
+        assert p["block_capacity"] * 48 <= budget // 4 + 48
+        assert p["block_capacity"] >= p["group_capacity"] >= 256
+        assert p["block_count"] >= 1 and p["group_count"] >= 1
+    # a tuning can shrink the block arena (never below a group arena)
+    p = ccd.plan_scratch(1000, 10 ** 6, mem_budget_bytes=budget, group_capacity=256,
+                         block_capacity=300)
+    assert p["block_capacity"] == 300 and p["group_capacity"] == 256
+    p = ccd.plan_scratch(1000, 10 ** 6, mem_budget_bytes=budget, group_capacity=4096,
+                         block_capacity=300)
+    assert p["block_capacity"] == 4096
+    # LDS frontier of the lane engine: two buffers of lane_capacity keys per thread
+    p = ccd.plan_scratch(1000, 100, lane_capacity=16)
+    assert p["lane_lds_bytes"] == 2 * 16 * 128 * 8
+    assert ccd.plan_scratch(1000, 100, lane_capacity=1000)["lane_lds_bytes"] == 2 * 32 * 128 * 8
+    # too small a budget, and bad arguments
+    with pytest.raises(ccd.CCDError) as e:
+        ccd.plan_scratch(10 ** 9, 100, mem_budget_bytes=1 << 20)
+    assert e.value.code == ccd.ENOMEM
+    for bad in ((-1, 10), (10, 0)):
+        with pytest.raises(ccd.CCDError) as e:
+            ccd.plan_scratch(*bad)
+        assert e.value.code == ccd.EINVAL
