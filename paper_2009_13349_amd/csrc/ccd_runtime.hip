@@ -226,8 +226,9 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
         set_last_error("scratch plan: device memory budget too small for the batch");
         return CCD_ENOMEM;
     }
-    size_t left = budget - fixed;
-    // block arena capacity: min(2 m_I + 2, tuning, a quarter of what is left)
+    size_t left = budget - fixed;  // >= per_group + min_block
+    // block arena capacity: min(2 m_I + 2, tuning, a quarter of what is left),
+    // never below a group arena's
     uint64_t want = max_iter_max >= (INT64_MAX - 2) / 2 ? (uint64_t)INT64_MAX
                                                         : (uint64_t)(2 * max_iter_max + 2);
     if (t.block_capacity > 0) want = std::min<uint64_t>(want, (uint64_t)t.block_capacity);
@@ -235,15 +236,17 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
     want = std::min<uint64_t>(want, quarter);
     P.block_cap = (int64_t)std::max<uint64_t>(want, (uint64_t)P.group_cap);
     const size_t per_block = smul((size_t)P.block_cap, kArenaBytesPerWord);
-    left -= per_block;  // one block arena always (<= left: quarter or per_group checked above)
+    // one arena of each engine always (per_block <= left / 4, or = per_group
+    // <= left / 2: both fit)
+    left -= per_group + per_block;
     // hand-off pool: the tuning's size, at most an eighth of what is left
     P.pool_words = std::min<int64_t>(t.handoff_words, (int64_t)(left / 8 / 8));
     left -= (size_t)P.pool_words * 8;
-    // the group engine carries the bulk of the work: it gets up to 3/4 of what
-    // is left; further blocks (rarely used) get the rest
-    const size_t groups_fit = std::max<size_t>(1, (left / 4 * 3) / per_group);
-    P.group_count = (int)std::min<size_t>((size_t)P.group_count, groups_fit);
-    left -= std::min(left, (size_t)P.group_count * per_group);
+    // the group engine carries the bulk of the work: further groups get up to
+    // 3/4 of what is left; further blocks (rarely used) the rest
+    const size_t more_groups = (left / 4 * 3) / per_group;
+    P.group_count = (int)std::min<size_t>((size_t)std::max(P.group_count, 1), 1 + more_groups);
+    left -= (size_t)(P.group_count - 1) * per_group;
     const size_t blocks_fit = 1 + left / per_block;
     P.block_count = (int)std::min<size_t>((size_t)P.block_count, blocks_fit);
     return CCD_OK;

@@ -111,6 +111,16 @@ def test_scratch_plan_sizes_are_overflow_safe(lib):
         assert p["block_capacity"] * 48 <= budget // 4 + 48
         assert p["block_capacity"] >= p["group_capacity"] >= 256
         assert p["block_count"] >= 1 and p["group_count"] >= 1
+    # the plan stays inside the budget at every batch size up to the largest
+    # it admits (one arena of each engine first, then the pool and the rest)
+    for b in (256 << 20, 1 << 30, 32 << 30):
+        for n in (1, 1000, 100_000, 900_000, 963_000, 4_000_000, 100_000_000):
+            try:
+                p = ccd.plan_scratch(n, 10 ** 6, mem_budget_bytes=b)
+            except ccd.CCDError as e:
+                assert e.code == ccd.ENOMEM
+                continue
+            assert p["bytes"] <= b, (b, n, p)
     # a tuning can shrink the block arena (never below a group arena)
     p = ccd.plan_scratch(1000, 10 ** 6, mem_budget_bytes=budget, group_capacity=256,
                          block_capacity=300)
