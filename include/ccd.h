@@ -234,6 +234,29 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa
               void* stream);
 
 /*
+ * Allocation-free ccd_batch, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same inputs, outputs, results and tuning as ccd_batch with
+ * on_device = 1 (device pointers only; CCD_EINVAL otherwise), asynchronous on
+ * `stream`, kernels launched one by one (never a graph of the library's own).
+ * It calls no hipMalloc, hipFree or other allocating routine: its scratch
+ * (counters, hand-off records, frontier arenas) is one static device array of
+ * 256 MiB per GPU, loaded with the library and held until the process ends.
+ * A batch whose scratch plan (ccd_plan_scratch with a 256 MiB budget) does
+ * not fit is rejected with CCD_ENOMEM before anything is launched; with the
+ * default tuning that is a batch of more than about 900,000 queries.  With
+ * per-query m_I (max_iter_q) the block engine's arena takes what the array
+ * allows and a query needing more returns with CCD_ST_OVERFLOW.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (the counters are cleared by a kernel at the start of each call):
+ * calls that overlap on one GPU, on any streams or contexts, race and must be
+ * serialised by the caller.  ccd_context_last_stats does not describe these
+ * calls.
+ */
+int ccd_batch_noalloc(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa* out,
+                      void* stream);
+
+/*
  * Autotuner: coordinate descent over the ccd_tuning knobs (group occupancy and
  * count, lane budget, lane capacity, lane waves per CU, group width), each
  * candidate timed (median of 3, after a warm-up) with events around whole

@@ -28,7 +28,7 @@ EXPORTED = [
     "ccd_context_enable_timing", "ccd_context_last_stats", "ccd_strerror", "ccd_last_error",
     "ccd_context_enable_graphs", "ccd_context_graph_counts", "ccd_autotune",
     "ccd_tuning_cache_store", "ccd_tuning_cache_load", "ccd_min_toi", "ccd_batch_indexed",
-    "ccd_scene_gamma", "ccd_plan_scratch",
+    "ccd_scene_gamma", "ccd_plan_scratch", "ccd_batch_noalloc",
 ]
 
 
@@ -128,6 +128,7 @@ def _lib():
         L.ccd_context_get_tuning.argtypes = [V, P(Tuning)]
         L.ccd_context_set_tuning.argtypes = [V, P(Tuning)]
         L.ccd_batch.argtypes = [V, P(BatchDesc), P(ResultSoA), V]
+        L.ccd_batch_noalloc.argtypes = [V, P(BatchDesc), P(ResultSoA), V]
         L.ccd_context_enable_timing.argtypes = [V, ctypes.c_int]
         L.ccd_context_enable_graphs.argtypes = [V, ctypes.c_int]
         L.ccd_autotune.argtypes = [V, P(BatchDesc), P(ResultSoA), V, ctypes.c_int, P(Tuning),
@@ -357,6 +358,22 @@ class Context:
                               ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:
             raise CCDError(rc, "ccd_batch")
+        self._keep = keep
+        return out
+
+    def batch_noalloc(self, pos, kind=None, default_kind=0, delta=1e-6, max_iter=1_000_000,
+                      min_sep=0.0, literal=False, delta_q=None, max_iter_q=None, min_sep_q=None,
+                      out: BatchResult | None = None, stream=None, t_max=1.0) -> BatchResult:
+        """ccd_batch_noalloc on device tensors (same arguments as batch_device;
+        the library allocates no device memory for it).  Pass `out` to keep the
+        call itself free of allocations on the Python side too."""
+        d, o, out, keep, stream = self._device_desc(
+            pos, kind, default_kind, delta, max_iter, min_sep, literal, delta_q, max_iter_q,
+            min_sep_q, out, stream, t_max)
+        rc = _lib().ccd_batch_noalloc(self._h, ctypes.byref(d), ctypes.byref(o),
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise CCDError(rc, "ccd_batch_noalloc")
         self._keep = keep
         return out
 

@@ -832,6 +832,125 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* o
 }
 
 // ---------------------------------------------------------------------------
+// Allocation-free batches.  The scratch of ccd_batch_noalloc is one static
+// device array per GPU (the code object's copy on each device), of kNoAllocBytes.
+// Host code never uses the array's name as an address: the device address of
+// each GPU's copy is looked up once per device (hipGetSymbolAddress, that
+// device current) and kept in g_noalloc_ptr.
+
+namespace {
+
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current), or null on failure.
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))
+            return nullptr;
+        g_noalloc_ptr[device] = p;
+    }
+    return g_noalloc_ptr[device];
+}
+
+// Carves the plan's buffers out of [base, base + bytes) at 256-byte offsets;
+// false if they do not fit.
+bool carve(const Plan& P, void* base, size_t bytes, Scratch& X) {
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = sadd(off, (b + 255) & ~(size_t)255);
+        return (unsigned char*)base + o;
+    };
+    X.counters = (unsigned long long*)take(64 * 8);
+    X.order = (int64_t*)take((size_t)P.n * 8);
+    X.rec_a = (uint64_t*)take(smul(smul((size_t)P.rec_a_cap, (size_t)P.rec_a_words), 8));
+    X.rec_b = (uint64_t*)take(smul(smul((size_t)P.rec_b_cap, (size_t)P.rec_b_words), 8));
+    X.pool = (uint64_t*)take(smul((size_t)P.pool_words, 8));
+    X.group_arena = (uint64_t*)take(smul((size_t)P.group_count * P.group_cap, kArenaBytesPerWord));
+    X.block_arena = (uint64_t*)take(smul((size_t)P.block_count * P.block_cap, kArenaBytesPerWord));
+    return off <= bytes;
+}
+
+}  // namespace
+
+extern "C" int ccd_batch_noalloc(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa* out,
+                                 void* stream) {
+    if (!ctx || !d || !out) {
+        set_last_error("ccd_batch_noalloc: null context, descriptor or outputs");
+        return CCD_EINVAL;
+    }
+    if (!d->on_device) {
+        set_last_error("ccd_batch_noalloc: inputs and outputs must be device memory");
+        return CCD_EINVAL;
+    }
+    if (d->n < 0 || !params_ok(d->params) || d->default_kind > 1 ||
+        (!d->max_iter_q && d->params.max_iter < 1)) {
+        set_last_error("ccd_batch_noalloc: negative count, bad parameters or kind");
+        return CCD_EINVAL;
+    }
+    if (d->n == 0) return CCD_OK;
+    if (!d->pos || !out->toi || !out->t_width || !out->hit || !out->n_checks || !out->status) {
+        set_last_error("ccd_batch_noalloc: null input or output array");
+        return CCD_EINVAL;
+    }
+    if (set_device(ctx->device) != CCD_OK) return CCD_EDEVICE;
+    void* base = noalloc_scratch(ctx->device);
+    if (!base) return CCD_EDEVICE;
+    const bool persistent = ctx->engine == CCD_ENGINE_PERSISTENT;
+    // per-query m_I are not read back (that would need a host buffer): the
+    // block arena then takes what the plan allows
+    const int64_t mi_max = d->max_iter_q ? INT64_MAX : d->params.max_iter;
+    Plan P;
+    // (the budget leaves room for the 256-byte alignment of the seven buffers)
+    if (plan_for(ctx->tune, ctx->num_cu, kNoAllocBytes - 7 * 256, d->n, mi_max, persistent, P) !=
+        CCD_OK) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "ccd_batch_noalloc: %lld queries need more scratch than the %zu MiB "
+                      "allocation-free array",
+                      (long long)d->n, kNoAllocBytes >> 20);
+        return CCD_ENOMEM;
+    }
+    Scratch X;
+    if (!carve(P, base, kNoAllocBytes, X)) {
+        set_last_error("ccd_batch_noalloc: scratch plan does not fit the static array");
+        return CCD_ENOMEM;
+    }
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = d->n;
+    a.pos = d->pos;
+    a.kind = d->kind;
+    a.delta_q = d->delta_q;
+    a.max_iter_q = d->max_iter_q;
+    a.min_sep_q = d->min_sep_q;
+    a.delta = d->params.delta;
+    a.max_iter = d->params.max_iter;
+    a.min_sep = d->params.min_sep;
+    a.t_max = d->params.t_max;
+    a.flags = d->params.flags;
+    a.default_kind = d->default_kind;
+    a.toi = out->toi;
+    a.t_width = out->t_width;
+    a.hit = out->hit;
+    a.n_checks = out->n_checks;
+    a.status = out->status;
+    // eager launches (a caller may be capturing the stream); the context's
+    // counters and graph are not touched, so ccd_context_last_stats does not
+    // describe this call
+    ctx->last_valid = false;
+    enqueue(ctx->tune, P, X, a, (hipStream_t)stream, persistent, false, nullptr);
+    return hip_ok(hipGetLastError(), "ccd_batch_noalloc launch") ? CCD_OK : CCD_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
 // Autotuner: coordinate descent over the launch/capacity knobs, each candidate
 // timed with events around whole batches.  Results do not depend on tuning, so
 // the search only trades speed.
