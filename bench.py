@@ -2,15 +2,23 @@
 
 One step = one ccd_batch call over the whole workload (all queries resident in
 HBM before the timed region), i.e. the complete root finder for every query:
-root pass (level 0 of every query), lane engine, group engine and block engine.  Default
-workload: 1,000,000 simulation-shaped queries (60% vertex-face, 40%
-edge-edge, 2% near-contacts, 1% grazing contacts), delta = 1e-6, m_I = 1e6,
-no minimum separation.  Prints one JSON line.
+root pass (level 0 of every query), lane engine, group engine and block
+engine.  Default workload: 1,000,000 simulation-shaped queries (60%
+vertex-face, 40% edge-edge, 2% near-contacts, 1% grazing contacts), delta =
+1e-6, m_I = 1e6, no minimum separation.  Prints one JSON line, which also
+carries per-workload lines for the other query sets (4,096 uniform
+vertex-face; 100,000 edge-edge with 10% degenerate cases; the four
+1,000,000-query minimum-separation runs), serving at three offered loads, and
+the CPU oracle's rate on the host (one pinned core, and K pinned processes on
+disjoint shards of the same sample).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -23,8 +31,117 @@ sys.path.insert(0, ROOT)
 METRIC = "CCD queries/s at delta=1e-6 (persistent vs plain kernel); p50/p99 serve latency"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk (FMA = 2)
 FLOP_PER_CHECK = {0: 227.0, 1: 177.0}  # vertex-face, edge-edge box check (binary64 add/sub/mul)
+FLOP_PER_CHECK_MS = 6.0                # enlargement by d (min_sep > 0)
 KERNELS = ("root", "lane", "group", "block")
+COMMITTED_TUNING = os.path.join(ROOT, "paper_2009_13349_amd", "tuning_mi355x.txt")
 
+
+# ---------------------------------------------------------------------------
+# CPU oracle workers.  They are forked before torch or the HIP library is
+# loaded (so no GPU state is copied), each pinned to one core, and wait for
+# work until the GPU measurements are over.
+
+def _oracle_worker(conn, core):
+    try:
+        os.sched_setaffinity(0, {core})
+    except OSError:
+        pass
+    import oracle
+    oracle.lib()
+    while True:
+        msg = conn.recv()
+        if msg is None:
+            break
+        pos, kind, kw = msg
+        t0 = time.perf_counter()
+        r = oracle.solve_batch(pos, kind, **kw)
+        dt = time.perf_counter() - t0
+        conn.send(({k: r[k] for k in ("toi", "t_width", "n_checks", "hit", "status")}, dt))
+
+
+class OracleWorkers:
+    def __init__(self, cores):
+        ctx = mp.get_context("fork")
+        self.cores = list(cores)
+        self.conns, self.procs = [], []
+        for c in self.cores:
+            a, b = ctx.Pipe()
+            p = ctx.Process(target=_oracle_worker, args=(b, c), daemon=True)
+            p.start()
+            self.conns.append(a)
+            self.procs.append(p)
+
+    def run(self, shards):
+        """shards: list (at most one per worker) of (pos, kind, kw); returns the
+        per-shard (results, seconds) and the wall time of the whole run."""
+        t0 = time.perf_counter()
+        for conn, sh in zip(self.conns, shards):
+            conn.send(sh)
+        out = [conn.recv() for conn, _ in zip(self.conns, shards)]
+        return out, time.perf_counter() - t0
+
+    def close(self):
+        for c in self.conns:
+            try:
+                c.send(None)
+            except OSError:
+                pass
+        for p in self.procs:
+            p.join(timeout=5)
+
+
+def _digest(parts):
+    h = hashlib.sha256()
+    for k in ("toi", "t_width", "n_checks", "hit", "status"):
+        a = np.concatenate([p[k] for p in parts])
+        if a.dtype == np.float64:
+            a = a.view(np.uint64)
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workers: OracleWorkers, w, seconds: float):
+    """The oracle (single-threaded C++, as it stands) on a seeded random sample
+    of the same workload: one pinned core over the whole sample, then K pinned
+    processes over disjoint shards of it; the two runs' results must hash the
+    same."""
+    from paper_2009_13349_amd import workloads as W
+    n = w["pos"].shape[1]
+    kw = dict(delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    perm = np.random.default_rng(1234).permutation(n)
+    pilot = W.subset(w, perm[:2000])
+    res, _ = workers.run([(pilot["pos"], pilot["kind"], kw)])
+    t_pilot = res[0][1]
+    m = int(min(n, max(2000, 2000 * seconds / max(t_pilot, 1e-3))))
+    ws = W.subset(w, perm[:m])
+    one, _ = workers.run([(ws["pos"], ws["kind"], kw)])
+    k = len(workers.cores)
+    cuts = np.array_split(np.arange(m), k)
+    shards = [(np.ascontiguousarray(ws["pos"][:, c]), np.ascontiguousarray(ws["kind"][c]), kw) for c in cuts]
+    many, tk = workers.run(shards)
+    h1 = _digest([one[0][0]])
+    hk = _digest([r[0] for r in many])
+    return {"value": round(m / one[0][1], 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} queries drawn uniformly at random (seed 1234) from the same {n}-query "
+                      f"workload; single-threaded C++ oracle pinned to one core, {one[0][1]:.1f} s",
+            "k_processes": {"value": round(m / tk, 2), "cores": k, "wall_s": round(tk, 2),
+                            "note": "the same sample in K disjoint shards, one pinned process each"},
+            "cpu_model": cpu_model(), "result_sha256": h1, "hash_equal": h1 == hk,
+            "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+# ---------------------------------------------------------------------------
+# GPU measurements
 
 def make_workload(name: str, n: int | None):
     from paper_2009_13349_amd import workloads as W
@@ -47,21 +164,23 @@ def run_engine(ctx, torch, pos, kind, w, engine, steps, warmup, timing=True, t_m
         out = ctx.batch_device(pos, kind, out=out, **kw)
         ctx.last_stats()
     torch.cuda.synchronize()
-    per_step = []
     stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
         out = ctx.batch_device(pos, kind, out=out, **kw)
         if timing:
             stats.append(ctx.last_stats())  # synchronises; reads the per-kernel HIP events
-        per_step.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     del ccd
     return (t1 - t0), stats, out
 
 
-def roofline(stats, kind_counts):
+def flop_per_check(kind: int, min_sep: float) -> float:
+    return FLOP_PER_CHECK[kind] + (FLOP_PER_CHECK_MS if min_sep > 0 else 0.0)
+
+
+def roofline(stats, min_sep: float = 0.0):
     """Dominant kernel (largest device time) and its achieved FP64 rate:
     algorithmic FLOPs (box checks executed by that kernel x FLOPs per check)
     per launch / average launch duration from HIP events."""
@@ -70,7 +189,7 @@ def roofline(stats, kind_counts):
     k = int(np.argmax(avg[1:])) + 1
     tier = k - 1
     checks = np.array([s["checks"][tier] for s in stats], dtype=np.float64).mean(axis=0)
-    flops = checks[0] * FLOP_PER_CHECK[0] + checks[1] * FLOP_PER_CHECK[1]
+    flops = checks[0] * flop_per_check(0, min_sep) + checks[1] * flop_per_check(1, min_sep)
     achieved = flops / (avg[k] * 1e-3) / 1e12
     return {
         "bound": "alu",
@@ -82,6 +201,7 @@ def roofline(stats, kind_counts):
         "traffic": None,
         "avg_launch_ms": round(float(avg[k]), 4),
         "checks_per_launch": [int(checks[0]), int(checks[1])],
+        "flop_per_check": [flop_per_check(0, min_sep), flop_per_check(1, min_sep)],
         "kernel_ms_avg": {KERNELS[i]: round(float(avg[i]), 4) for i in range(4)},
     }
 
@@ -90,76 +210,140 @@ def kernel_symbol(tier: int, tuning: dict) -> str:
     if tier == 0:
         return "ccd::k_lane<true>"
     if tier == 2:
-        return "ccd::k_group<8, 1>"
+        return f"ccd::k_group<8, 1, {'true' if tuning['block_lds_words'] > 0 else 'false'}>"
     gw = tuning["group_waves"]
-    return f"ccd::k_group<{gw}, {tuning['group_occupancy'] if gw == 1 else 1}>"
+    occ = tuning["group_occupancy"] if gw == 1 else 1
+    lds = tuning["group_lds_words"] > 0 and (gw == 8 or (gw == 1 and occ == 3))
+    return f"ccd::k_group<{gw}, {occ}, {'true' if lds else 'false'}>"
 
 
-def hbm_record(symbol: str):
-    """Per-launch HBM bytes {fetch_bytes, write_bytes} (FETCH_SIZE, WRITE_SIZE,
-    copy-calibrated) recorded under profiles/ for these exact kernel sources,
-    else None."""
+def profile_record(fname: str, symbol: str, tuning: dict):
+    """A per-kernel record under profiles/ taken with these exact kernel
+    sources (else None), and whether its tuning is the one in use."""
     from paper_2009_13349_amd.rocprof_summary import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
-        return None
+        return None, False
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None, False
+    k = rec.get("kernels", {}).get(symbol)
+    same = rec.get("tuning") is not None and all(rec["tuning"].get(f) == v for f, v in tuning.items())
+    return k, same
+
+
+def executed_fp64(symbol: str, tuning: dict, avg_ms: float):
+    """FP64 FLOP/s the dominant kernel executed (rocprofv3 counters of these
+    kernel sources: 64 x (ADD_F64 + MUL_F64 + 2 FMA_F64) wave instructions per
+    dispatch) over its launch time, and its VALU issue share."""
+    k, same = profile_record("fp64_counters.json", symbol, tuning)
+    if not k:
         return None
-    k = rec["kernels"].get(symbol)
-    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
-        return None
-    return k
+    add, mul, fma = (k.get("SQ_INSTS_VALU_ADD_F64", 0.0), k.get("SQ_INSTS_VALU_MUL_F64", 0.0),
+                     k.get("SQ_INSTS_VALU_FMA_F64", 0.0))
+    flops = 64.0 * (add + mul + 2.0 * fma)
+    out = {"tflops": round(flops / (avg_ms * 1e-3) / 1e12, 3), "flop_per_launch": flops,
+           "frac_of_peak": round(flops / (avg_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 5),
+           "counters_tuning_matches": same}
+    valu, grbm = k.get("SQ_INSTS_VALU"), k.get("GRBM_GUI_ACTIVE")
+    if valu and grbm:
+        # 4 cycles per wave64 VALU instruction on 1,024 SIMDs; GRBM_GUI_ACTIVE
+        # sums the dispatch's cycles over the 8 XCDs
+        out["valu_busy"] = round(4.0 * valu / (1024.0 * grbm / 8.0), 3)
+        out["fp64_share_of_valu"] = round((add + mul + fma) / valu, 3)
+    return out
 
 
-def hbm_traffic(symbol: str):
-    k = hbm_record(symbol)
-    return k["fetch_bytes"] + k["write_bytes"] if k else None
-
-
-def query_streaming(stats, n: int):
+def query_streaming(stats, n: int, tuning: dict):
     """The root pass reads every query's 24 coordinates and its kind once:
     its read rate against the 8 TB/s HBM peak."""
     ms = float(np.mean([s["kernel_ms"][0] for s in stats]))
     bytes_in = n * (24 * 8 + 1)
     gbps = bytes_in / (ms * 1e-3) / 1e9
-    k = hbm_record("ccd::k_root")
+    k, _ = profile_record("hbm_traffic.json", "ccd::k_root", tuning)
     return {"kernel": "root", "algorithmic_bytes_read": bytes_in, "avg_launch_ms": round(ms, 4),
             "gbps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / 8000.0, 3),
             "measured_read_bytes": round(k["fetch_bytes"]) if k else None}
 
 
-def cpu_baseline(w, seconds: float):
-    """The oracle (single thread, as it stands) on a seeded random sample of
-    the same workload, scaled to queries/s."""
-    import oracle
-    from paper_2009_13349_amd import workloads as W
+def apply_tuning(ctx, args, key, w, pos, kind):
+    """Tuning order: --tuning, the committed MI355X tuning file, the user cache,
+    then a search (stored in the user cache)."""
+    from paper_2009_13349_amd import ccd
+    if args.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+        return {"source": "command line", "tuning": ctx.tuning()}
+    if not args.retune:
+        if os.path.exists(COMMITTED_TUNING) and ctx.tuning_cache_load(COMMITTED_TUNING, key):
+            return {"source": "committed tuning file (autotuner result on MI355X)", "key": key,
+                    "tuning": ctx.tuning()}
+        if ctx.tuning_cache_load(args.tuning_cache, key):
+            return {"source": "cache", "key": key, "tuning": ctx.tuning()}
+    if args.no_autotune:
+        return {"source": "defaults", "tuning": ctx.tuning()}
+    ctx.set_engine(ccd.ENGINE_PERSISTENT)
+    t0 = time.perf_counter()
+    best, best_ms = ctx.autotune(pos, kind, delta=w["delta"], max_iter=w["max_iter"], min_sep=w["min_sep"])
+    os.makedirs(os.path.dirname(args.tuning_cache) or ".", exist_ok=True)
+    ctx.tuning_cache_store(args.tuning_cache, key)
+    return {"source": "search", "key": key, "seconds": round(time.perf_counter() - t0, 2),
+            "best_ms": round(best_ms, 3), "tuning": best}
+
+
+def measure_workload(ctx, torch, w, steps, warmup):
+    """One query set: persistent engine, per-kernel events; its own roofline."""
+    from paper_2009_13349_amd import ccd
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    kind = torch.from_numpy(w["kind"]).to(dev)
     n = w["pos"].shape[1]
-    rng = np.random.default_rng(1234)
-    perm = rng.permutation(n)
-    done, t_used, chunk = 0, 0.0, 2000
-    while t_used < seconds and done < n:
-        idx = perm[done:done + chunk]
-        ws = W.subset(w, idx)
-        t0 = time.perf_counter()
-        oracle.solve_batch(ws["pos"], ws["kind"], delta=w["delta"], max_iter=w["max_iter"],
-                           min_sep=w["min_sep"])
-        t_used += time.perf_counter() - t0
-        done += len(idx)
-    return {"value": round(done / t_used, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} queries drawn uniformly at random (seed 1234) from the same "
-                      f"{n}-query workload, single-threaded C++ oracle, {t_used:.1f} s"}
+    t, stats, out = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, steps, warmup)
+    seq = float(out.n_checks.to(torch.float64).sum().item())
+    rl = roofline(stats, w["min_sep"])
+    tier = KERNELS.index(rl["kernel"]) - 1
+    rl["symbol"] = kernel_symbol(tier, ctx.tuning())
+    res = {"queries": n, "value": round(n * steps / t, 1), "ms_per_step": round(1e3 * t / steps, 3),
+           "steps": steps, "delta": w["delta"], "max_iter": w["max_iter"], "min_sep": w["min_sep"],
+           "hits": int(out.hit.sum().item()),
+           "capped": int(((out.status & 1) != 0).sum().item()),
+           "overflowed": stats[-1]["overflowed"],
+           "box_checks_per_step": int(sum(sum(c) for c in stats[-1]["checks"])),
+           "sequential_checks_per_step": int(seq),
+           "promoted_per_step": stats[-1]["promoted"], "level_probes_per_step": stats[-1]["probes"],
+           "roofline": rl}
+    del pos, kind, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_configs(ctx, torch, steps):
+    """The other query sets of the benchmark, each with the main workload's
+    tuning: 4,096 uniform vertex-face queries; 100,000 edge-edge queries with
+    10% degenerate cases (their parallel and coplanar pairs run to the m_I cap);
+    1,000,000 minimum-separation queries at d in {1e-4, 1e-3} x delta in
+    {1e-6, 1e-4}."""
+    from paper_2009_13349_amd import workloads as W
+    out = {}
+    w = W.uniform_vf(4096, seed=0)
+    out[w["name"]] = measure_workload(ctx, torch, w, max(steps, 20), 3)
+    w = W.edge_edge_mixed(100_000, seed=1)
+    out[w["name"]] = measure_workload(ctx, torch, w, max(2, steps // 4), 1)
+    for d in (1e-4, 1e-3):
+        for delta in (1e-6, 1e-4):
+            w = W.min_separation(1_000_000, seed=2, d_min=d, delta=delta)
+            out[w["name"]] = measure_workload(ctx, torch, w, 2, 1)
+            del w
+    return out
 
 
 def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, load: float = 0.7,
-                  seed: int = 4, streams: int = 2):
+                  seed: int = 4, streams: int = 2, launch_target_us: int = 5000):
     """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
     log-uniform in [1e-6, 1e-4]) at `load` x the measured batch throughput,
     submitted to the continuous-batching server; latency = scheduled arrival ->
     results in the caller's arrays.  Request payloads are contiguous pinned
     slices of the benchmark workload (a fixed set of `payloads` of them,
     reused round robin)."""
-    import math
     from paper_2009_13349_amd import ccd
     rng = np.random.default_rng(seed)
     N = w["pos"].shape[1]
@@ -175,8 +359,8 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
     gaps = rng.exponential(1.0 / lam, size=requests)
     deltas = np.exp(rng.uniform(math.log(1e-6), math.log(1e-4), size=requests))
     srv = ccd.Server(streams=streams, pool_bytes=16 << 30, scratch_bytes=12 << 30,
-                     max_queries_per_launch=4_000_000)
-    # warm-up: one request of each payload size, not timed
+                     max_queries_per_launch=4_000_000, launch_target_us=launch_target_us)
+    # warm-up: a few requests, not timed (they also seed the cost estimate)
     for n, pos, kind in pay[:4]:
         srv.wait(srv.submit(pos, kind, delta=1e-6), 600_000)
     t0 = time.monotonic() + 0.05
@@ -202,11 +386,11 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
             "mean_request_queries": round(mean_n, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3),
             "queries_per_s": round(qsum / (t_end - t0), 1), "launches": st["launches"],
-            "pool_peak_bytes": st["pool_peak"],
+            "launch_target_us": launch_target_us, "pool_peak_bytes": st["pool_peak"],
             "latency": "scheduled arrival -> results in the caller's host arrays"}
 
 
-def measure_extras(ctx, torch, pos, kind, w, n, steps):
+def measure_extras(ctx, torch, pos, kind, w, n, steps, args):
     """The line search's shortened interval (Sec. 7.2): the same queries over t in
     [0, 0.5], then the batch-wide smallest toi (the step bound); the indexed
     form with a scene-wide filter; and the host-pointer form."""
@@ -224,7 +408,7 @@ def measure_extras(ctx, torch, pos, kind, w, n, steps):
                  "ms_per_step": round(1e3 * t_s / steps, 3),
                  "hits": int(out_s.hit.sum().item()), "min_toi": float(mt.item()),
                  "min_toi_ms": round(ev0.elapsed_time(ev1) / 10, 4)}
-    return shortened, measure_indexed(ctx, torch, steps), measure_host(ctx, w, n)
+    return shortened, measure_indexed(ctx, torch, steps, args), measure_host(ctx, w, n)
 
 
 def measure_host(ctx, w, n, runs: int = 2):
@@ -245,15 +429,27 @@ def measure_host(ctx, w, n, runs: int = 2):
             "note": "host arrays in, host arrays out (validation + PCIe copies included)"}
 
 
-def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
+def measure_indexed(ctx, torch, steps, args, n_pairs=1_000_000):
     """Candidate pairs over shared vertex arrays with a scene-wide filter (the
     mesh form of Sec. 7): a two-sheet mesh scene of n_pairs broad-phase pairs,
-    gamma from ccd_scene_gamma, then ccd_batch_indexed (gather + root finder)."""
+    gamma from ccd_scene_gamma, then ccd_batch_indexed (gather + root finder),
+    with a tuning of its own (searched on the scene's pairs in
+    structure-of-arrays form, stored under the scene's key)."""
     from paper_2009_13349_amd import ccd, workloads as W
     s = W.mesh_scene(n_pairs, seed=5)
     dev = torch.device("cuda:0")
     v0, v1 = torch.from_numpy(s["v0"]).to(dev), torch.from_numpy(s["v1"]).to(dev)
     ids, kind = torch.from_numpy(s["ids"]).to(dev), torch.from_numpy(s["kind"]).to(dev)
+    main_tuning = ctx.tuning()
+    tune = None
+    if not args.tuning:
+        # the pairs' coordinates as a structure-of-arrays batch for the tuner
+        gathered = np.concatenate([s["v0"][s["ids"][:, k]].T for k in range(4)] +
+                                  [s["v1"][s["ids"][:, k]].T for k in range(4)])
+        pos = torch.from_numpy(np.ascontiguousarray(gathered)).to(dev)
+        tune = apply_tuning(ctx, args, f"{s['name']}_delta1e-06",
+                            {"delta": 1e-6, "max_iter": 1_000_000, "min_sep": 0.0}, pos, kind)
+        del pos, gathered
     ctx.set_engine(ccd.ENGINE_PERSISTENT)
     ctx.enable_timing(False)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -270,32 +466,39 @@ def measure_indexed(ctx, torch, steps, n_pairs=1_000_000):
         out = ctx.batch_indexed(v0, v1, ids, kind, gamma=g, out=out)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    ctx.set_tuning(**main_tuning)
     return {"workload": s["name"], "vertices": int(s["v0"].shape[0]), "value": round(n_pairs * steps / t, 1),
             "ms_per_step": round(1e3 * t / steps, 3), "hits": int(out.hit.sum().item()),
-            "scene_gamma_ms": round(gamma_ms, 4), "gamma": [float(x) for x in g.cpu().numpy()]}
+            "scene_gamma_ms": round(gamma_ms, 4), "gamma": [float(x) for x in g.cpu().numpy()],
+            "autotune": tune}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="simulation", choices=["simulation", "edge_edge", "uniform_vf"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="K of the K-process oracle run (capped by the cores this process may use)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-workload lines")
     ap.add_argument("--tuning", default="", help="k=v,... overrides of ccd_tuning")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the autotuner (default: tune once per device and workload, cached)")
+                    help="use the library defaults when no stored tuning matches")
+    ap.add_argument("--retune", action="store_true", help="search again instead of stored tunings")
     ap.add_argument("--tuning-cache", default=os.environ.get(
         "CCD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ccd_mi355x_tuning.txt")))
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the serving measurement (0: skip)")
-    ap.add_argument("--serve-streams", type=int, default=2,
-                    help="compute streams of the serving measurement's server")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests per offered load of the serving measurement (0: skip)")
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9")
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-target-us", type=int, default=5000,
+                    help="server's launch latency target (0: launches bounded by size only)")
     ap.add_argument("--main-only", action="store_true",
-                    help="time only the benchmark workload's batches (for profiler runs): no "
-                         "shortened-interval or indexed measurement")
+                    help="time only the benchmark workload's batches (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -304,6 +507,12 @@ def main():
               "each run the same batch call on a slice of the query index, with no cross-GPU "
               "step to measure.", file=sys.stderr)
         raise SystemExit(2)
+
+    # the oracle's worker processes start before torch and the HIP library load
+    workers = None
+    if args.cpu_seconds > 0 and not args.main_only:
+        cores = sorted(os.sched_getaffinity(0))[:max(1, args.cpu_procs)]
+        workers = OracleWorkers(cores)
 
     import torch
     from paper_2009_13349_amd import ccd
@@ -325,22 +534,9 @@ def main():
         del src, dst
 
     ctx = ccd.Context(0, mem_budget_bytes=32 << 30)
-    autotune = None
-    if args.tuning:
-        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
-    elif not args.no_autotune:
-        key = f"{w['name']}_delta{w['delta']:g}"
-        if ctx.tuning_cache_load(args.tuning_cache, key):
-            autotune = {"source": "cache", "tuning": ctx.tuning()}
-        else:
-            ctx.set_engine(ccd.ENGINE_PERSISTENT)
-            t0 = time.perf_counter()
-            best, best_ms = ctx.autotune(pos, kind, delta=w["delta"], max_iter=w["max_iter"],
-                                         min_sep=w["min_sep"])
-            autotune = {"source": "search", "seconds": round(time.perf_counter() - t0, 2),
-                        "best_ms": round(best_ms, 3), "tuning": best}
-            os.makedirs(os.path.dirname(args.tuning_cache) or ".", exist_ok=True)
-            ctx.tuning_cache_store(args.tuning_cache, key)
+    key = f"{w['name']}_delta{w['delta']:g}"
+    autotune = apply_tuning(ctx, args, key, w, pos, kind)
+    tuning = ctx.tuning()
     t_p, stats_p, out = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PERSISTENT, args.steps,
                                    args.warmup)
     hits = int(out.hit.sum().item())
@@ -356,23 +552,41 @@ def main():
     if not args.no_plain:
         t_b, stats_b, _ = run_engine(ctx, torch, pos, kind, w, ccd.ENGINE_PLAIN, args.steps,
                                      args.warmup)
+        kms = {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4) for i in range(4)}
+        handed = stats_b[-1]["promoted"][0]
         plain = {"value": round(n * args.steps / t_b, 1), "ms_per_step": round(1e3 * t_b / args.steps, 3),
-                 "kernel_ms_avg": {KERNELS[i]: round(float(np.mean([s["kernel_ms"][i] for s in stats_b])), 4)
-                                   for i in range(4)}}
+                 "kernel_ms_avg": kms,
+                 "lane_kernel_only": {
+                     "ms": kms["lane"], "queries_finished": n - handed, "queries_handed_on": handed,
+                     "note": "the plain kernel itself: one thread per query, a frontier of up to "
+                             "lane_capacity boxes in LDS; a query whose level outgrows it goes to "
+                             "the group tier, whose time is in the whole-path figure"}}
+        ctx.set_engine(ccd.ENGINE_PERSISTENT)
     shortened = indexed = host = None
     if not args.main_only:
-        shortened, indexed, host = measure_extras(ctx, torch, pos, kind, w, n, args.steps)
-    rl = roofline(stats_p, kind_counts)
+        shortened, indexed, host = measure_extras(ctx, torch, pos, kind, w, n, args.steps, args)
+        ctx.set_tuning(**tuning)
+    rl = roofline(stats_p)
     tier = KERNELS.index(rl["kernel"]) - 1
-    rl["symbol"] = kernel_symbol(tier, ctx.tuning())
-    tb = hbm_traffic(rl["symbol"])
+    rl["symbol"] = kernel_symbol(tier, tuning)
+    tk, same = profile_record("hbm_traffic.json", rl["symbol"], tuning)
+    tb = tk["fetch_bytes"] + tk["write_bytes"] if tk and tk.get("fetch_bytes") is not None else None
     rl["traffic"] = round(tb) if tb else None
     rl["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    rl["traffic_tuning_matches"] = same if tb else None
     rl["hbm_gbps"] = round(tb / (rl["avg_launch_ms"] * 1e-3) / 1e9, 1) if tb else None
-    streaming = query_streaming(stats_p, n)
+    rl["executed"] = executed_fp64(rl["symbol"], tuning, rl["avg_launch_ms"])
+    streaming = query_streaming(stats_p, n, tuning)
     checks_total = int(sum(sum(c) for c in stats_p[-1]["checks"]))
     alg_flops = alg_checks[0] * FLOP_PER_CHECK[0] + alg_checks[1] * FLOP_PER_CHECK[1]
     path_alg_tflops = alg_flops / (t_p / args.steps) / 1e12
+    del pos, kind, out, nck
+    torch.cuda.empty_cache()
+
+    configs = None
+    if not args.main_only and not args.no_configs and args.workload == "simulation":
+        configs = measure_configs(ctx, torch, args.steps)
+        ctx.set_tuning(**tuning)
     ctx.close()
 
     line = {
@@ -402,6 +616,8 @@ def main():
         "sequential_checks_per_step": int(sum(alg_checks)),
         "path_algorithmic_tflops": round(path_alg_tflops, 3),
         "promoted_per_step": stats_p[-1]["promoted"],
+        "level_probes_per_step": stats_p[-1]["probes"],
+        "overflowed_per_step": stats_p[-1]["overflowed"],
         "lane_utilization": [round(sum(stats_p[-1]["checks"][i]) / stats_p[-1]["lane_slots"][i], 3)
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,
@@ -409,10 +625,19 @@ def main():
         "shortened_interval": shortened,
         "indexed": indexed,
         "host_pointers": host,
+        "configs": configs,
     }
-    line["serve"] = (serve_latency(w, torch, value, args.serve_requests, streams=args.serve_streams)
-                     if args.serve_requests > 0 and args.workload == "simulation" else None)
-    line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    loads = [float(x) for x in args.serve_loads.split(",") if x]
+    if args.serve_requests > 0 and args.workload == "simulation" and not args.main_only:
+        runs = [serve_latency(w, torch, value, args.serve_requests, load=ld, streams=args.serve_streams,
+                              launch_target_us=args.serve_target_us) for ld in loads]
+        line["serve"] = min(runs, key=lambda r: abs(r["offered_load"] - 0.7))
+        line["serve_loads"] = runs
+    else:
+        line["serve"] = None
+    line["cpu_baseline"] = cpu_baseline(workers, w, args.cpu_seconds) if workers else None
+    if workers:
+        workers.close()
     print(json.dumps(line), flush=True)
 
 

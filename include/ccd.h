@@ -163,6 +163,13 @@ typedef struct ccd_tuning {
                                      from the group to the block engine; when it is full
                                      the block engine restarts such a query at level 0
                                      (same results, more work).  Default 2^25. */
+    int32_t group_lds_words;      /* the first words of each level of a wide query stay in LDS
+                                     (two buffers per group; the rest of a level spills to
+                                     the HBM arena), for one-wave groups at occupancy 3 and
+                                     eight-wave groups.  Default 0 (off); clamped to what a
+                                     workgroup can hold beside the kernel's own LDS; rounded
+                                     down to a multiple of 64 words per wave of the group. */
+    int32_t block_lds_words;      /* the same for the huge-query engine.  Default 2048. */
 } ccd_tuning;
 int ccd_context_get_tuning(ccd_context* ctx, ccd_tuning* out);
 int ccd_context_set_tuning(ccd_context* ctx, const ccd_tuning* t);
@@ -258,7 +265,8 @@ int ccd_batch_noalloc(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_re
 
 /*
  * Autotuner: coordinate descent over the ccd_tuning knobs (group occupancy and
- * count, lane budget, lane capacity, lane waves per CU, group width), each
+ * count, lane budget, lane capacity, lane waves per CU, group width, group
+ * LDS words), each
  * candidate timed (median of 3, after a warm-up) with events around whole
  * ccd_batch calls of the given device batch on `stream`; a candidate must be
  * 2% faster to be taken, and the winner is confirmed against the starting
@@ -303,6 +311,8 @@ typedef struct ccd_stats {
     uint64_t restarted;      /* group -> block hand-offs restarted at level 0 (pool full) */
     uint64_t deep;           /* lane -> group hand-offs because a level reached depth sum 64 */
     uint64_t handoff_words;  /* pool words the group -> block hand-offs asked for */
+    uint64_t probes[2];      /* level probes of the wide engines: run, and decided the level
+                                without checking it in full */
 } ccd_stats;
 int ccd_context_enable_timing(ccd_context* ctx, int enable);
 int ccd_context_last_stats(ccd_context* ctx, ccd_stats* out);
@@ -390,7 +400,10 @@ typedef struct ccd_serve_config {
     int32_t device;
     int32_t streams;                /* compute streams (1..4), default 2 */
     int32_t max_requests;           /* requests per launch, default 1024 */
-    int32_t reserved;
+    int32_t launch_target_us;       /* latency bound: a launch takes at most as many queries as
+                                       fill this much device time, from the device time per
+                                       query measured on earlier launches (at least one
+                                       request per launch); 0: off.  Default 5000 */
     int64_t max_queries_per_launch; /* default 4,000,000 (a larger single request still runs) */
     size_t pool_bytes;              /* device memory for resident requests, default 8 GiB */
     size_t scratch_bytes;           /* scratch budget per compute stream, default 12 GiB */

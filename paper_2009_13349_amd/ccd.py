@@ -59,7 +59,8 @@ class Tuning(ctypes.Structure):
                 ("lane_budget", ctypes.c_int64), ("group_waves", ctypes.c_int32),
                 ("group_count", ctypes.c_int32), ("group_capacity", ctypes.c_int64),
                 ("block_count", ctypes.c_int32), ("group_occupancy", ctypes.c_int32),
-                ("block_capacity", ctypes.c_int64), ("handoff_words", ctypes.c_int64)]
+                ("block_capacity", ctypes.c_int64), ("handoff_words", ctypes.c_int64),
+                ("group_lds_words", ctypes.c_int32), ("block_lds_words", ctypes.c_int32)]
 
 
 class ScratchPlan(ctypes.Structure):
@@ -95,7 +96,7 @@ class Stats(ctypes.Structure):
                 ("lane_slots", ctypes.c_uint64 * 3), ("kernel_ms", ctypes.c_float * 4),
                 ("reserved", ctypes.c_uint32), ("overflowed", ctypes.c_uint64),
                 ("restarted", ctypes.c_uint64), ("deep", ctypes.c_uint64),
-                ("handoff_words", ctypes.c_uint64)]
+                ("handoff_words", ctypes.c_uint64), ("probes", ctypes.c_uint64 * 2)]
 
 
 _LIB = None
@@ -275,7 +276,8 @@ class Context:
                "lane_slots": [int(x) for x in s.lane_slots],
                "kernel_ms": [float(x) for x in s.kernel_ms], "overflowed": int(s.overflowed),
                "restarted": int(s.restarted), "deep": int(s.deep),
-               "handoff_words": int(s.handoff_words), "rc": rc}
+               "handoff_words": int(s.handoff_words),
+               "probes": [int(s.probes[0]), int(s.probes[1])], "rc": rc}
         if rc not in (OK,):
             raise CCDError(rc, "ccd batch counters")
         return out
@@ -499,7 +501,7 @@ class Context:
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("streams", ctypes.c_int32),
-                ("max_requests", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_requests", ctypes.c_int32), ("launch_target_us", ctypes.c_int32),
                 ("max_queries_per_launch", ctypes.c_int64), ("pool_bytes", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t)]
 
@@ -553,13 +555,15 @@ class Server:
     """Continuous-batching server (ccd_serve_*) on one GPU."""
 
     def __init__(self, device=0, streams=2, pool_bytes=8 << 30, scratch_bytes=12 << 30,
-                 max_queries_per_launch=4_000_000, max_requests=1024):
+                 max_queries_per_launch=4_000_000, max_requests=1024, launch_target_us=None):
         L = _serve_lib()
         c = ServeConfig()
         L.ccd_serve_config_default(ctypes.byref(c))
         c.device, c.streams, c.max_requests = device, streams, max_requests
         c.max_queries_per_launch, c.pool_bytes, c.scratch_bytes = (
             max_queries_per_launch, pool_bytes, scratch_bytes)
+        if launch_target_us is not None:
+            c.launch_target_us = int(launch_target_us)
         h = ctypes.c_void_p()
         rc = L.ccd_serve_open(ctypes.byref(c), ctypes.byref(h))
         if rc != OK:

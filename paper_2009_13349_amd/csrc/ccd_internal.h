@@ -19,6 +19,8 @@ enum Counter : int {
     kCntPool = kCntSlots + 3,    // words taken from the group -> block hand-off pool
     kCntRestart,         // group -> block hand-offs that restart at level 0 (pool full)
     kCntDeep,            // lane engine: queries handed on because a level passed depth sum 64
+    kCntProbe,           // group engines: level probes run
+    kCntProbeHit,        // group engines: level probes that decided the level
     kCntEnd,
 };
 static_assert(kCntEnd <= 64, "counters are cleared by one wavefront");
@@ -111,6 +113,8 @@ struct LaneCfg {
 
 struct GroupCfg {
     int64_t capacity;          // words per level of one group's arena buffer
+    int64_t lds_words;         // the first lds_words words of a packed level stay in LDS
+                               // (two buffers per block, dynamic shared memory)
     uint64_t* arena;           // [groups][2][3][capacity]
     const uint64_t* in_records;
     int64_t in_record_words;

@@ -997,18 +997,45 @@ __device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
 // Pair words (kFmtPair): the flag bit marks a pair whose child 1 passed the prism test.
 constexpr uint64_t kPairFlag = 1ull << 63;  // the pair's child 1 passed the prism test
 
+// One buffer of a group arena.  Word i of a packed level (keys or pair words)
+// is in LDS when i < nl and in HBM (at the same index) otherwise: the first nl
+// words of every level never leave the CU.  Triple levels (three HBM arrays
+// of cap words) use nl = 0.
+// (The two pointers carry their address spaces so that the compiler keeps an
+// LDS access and a global access apart instead of merging them into one flat
+// access through a selected pointer.)
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(1))) uint64_t hbm_u64;
+
+struct Buf {
+    lds_u64* lds;
+    hbm_u64* hbm;
+    int64_t nl;
+    __device__ __forceinline__ uint64_t get(int64_t i) const {
+        uint64_t v;
+        if (i < nl) v = lds[i];
+        else v = hbm[i];
+        return v;
+    }
+    __device__ __forceinline__ void put(int64_t i, uint64_t v) const {
+        if (i < nl) lds[i] = v;
+        else hbm[i] = v;
+    }
+};
+
 template <int W>
 struct GroupShared {
     double Xs[24];  // the query's coordinates, Xs[c*8 + k]
     double Es[3];   // eps per axis
     Acc acc[W];
     KeyAcc kacc[W];
-    unsigned long long sum[W][2];
+    unsigned long long sum[W][3];
     unsigned long long next_cnt;  // W > 1: words of the next level
     unsigned long long next_box;  // W > 1: boxes of the next level
     int64_t rec;
     int64_t ho[2];      // hand-off: record index and pool offset (or -1)
     uint64_t cand[64];  // head try: unchecked words below the running first colliding key
+    unsigned int ncand; // cap-level probe: candidates gathered
 };
 
 // ---------------------------------------------------------------------------
@@ -1155,12 +1182,13 @@ struct LaneBoxes {
 // second loop takes the remaining chunks: the rarely run head-try code is then
 // not part of the hot loop (which spills less for it).
 template <int W, int KIND, int FIN, int SPLIT, bool OP>
-__device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
+__device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, const Buf& nt,
                                            int64_t cap, const State& S, int64_t words,
                                            const LevelInfo& L, double min_sep, double delta,
                                            bool cap_level, bool literal, int64_t max_iter, Acc& A,
                                            uint64_t& next_words, uint64_t& next_boxes,
-                                           bool& early, Outcome& Oe, uint64_t& checked) {
+                                           bool& early, Outcome& Oe, uint64_t& checked,
+                                           unsigned long long* a_counters) {
     constexpr int T = 64 * W;
     constexpr bool kPacked = FIN != kFmtTriple;
     constexpr bool kPair = FIN == kFmtPair;
@@ -1190,9 +1218,16 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
     }
 
     // the boxes of the word at index i (FIN's format) and their checks
-    auto load = [&](int64_t i, uint64_t& p0, uint64_t& p1, uint64_t& p2) {
-        p0 = ct[i];
-        if (!kPacked) { p1 = ct[cap + i]; p2 = ct[2 * cap + i]; }
+    // (c0: the chunk's first word, wave-uniform; a chunk lies wholly in LDS or
+    // wholly in HBM because the LDS part is a multiple of T words)
+    auto load = [&](int64_t c0, uint64_t& p0, uint64_t& p1, uint64_t& p2) {
+        const int64_t i = c0 + tid;
+        if (kPacked) {
+            if (c0 < ct.nl) p0 = ct.lds[i];
+            else p0 = ct.hbm[i];
+        } else {
+            p0 = ct.hbm[i]; p1 = ct.hbm[cap + i]; p2 = ct.hbm[2 * cap + i];
+        }
     };
     auto expand = [&](bool act, uint64_t p0, uint64_t p1, uint64_t p2, LaneBoxes& B) {
         B.act[0] = act;
@@ -1240,8 +1275,167 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         }
     };
 
+    // Level probe of the multi-wave groups (which have no head try).  Alg. 2
+    // ends a level at its first colliding box f (carried box first, m_I
+    // reached at f, f terminal) or, on a level where m_I can stop the query
+    // (N + |level| >= m_I), at the first colliding box whose rank is at least
+    // m_I - N - 1, with t_lo(f) either way; only when neither happens does the
+    // level go on to the next.  So f with its rank, and on such a level any
+    // colliding box of large enough rank, decide the level without checking
+    // the boxes in between.  When the level's first chunk (which holds its
+    // smallest key) shows a colliding box that could end the query, or on an
+    // m_I level, the probe checks that chunk and (m_I level) the last one
+    // (keys of large rank), counts ranks with one pass over the keys, checks
+    // the unprobed boxes below the smallest colliding probe box (so that f is
+    // exact), and returns the decision if it is proven; otherwise the level is
+    // checked in full as usual.  (Single-wave groups stop the same levels
+    // with the head try below; measured, a probe there costs more in register
+    // pressure than it saves.)
+    if (kPacked && W > 1) {
+        const uint64_t mI = (uint64_t)max_iter;
+        const int64_t c1 = (cap_level && words > T) ? ((words - 1) / T) * T : 0;  // last chunk
+        KeyAcc P;
+        keyacc_init(P);
+        unsigned long long nprobe = 0;
+        bool ends = cap_level;
+        for (int pc = 0; pc < 2; ++pc) {
+            const int64_t c = pc == 0 ? 0 : c1;
+            if (pc == 1 && c1 == 0) break;
+            uint64_t q0 = 0, q1 = 0, q2 = 0;
+            const bool act = c + tid < words;
+            if (act) load(c, q0, q1, q2);
+            LaneBoxes B;
+            expand(act, q0, q1, q2, B);
+            check(B);
+            nprobe += (B.act[0] ? 1 : 0) + (B.act[1] ? 1 : 0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (!B.R[b].collide) continue;
+                const bool tb = B.R[b].small || L.dcap;
+                keyacc_add(P, B.key[b], B.it[b], tb, B.R[b].small, true, -1);
+                ends = ends || tb || (!literal && S.tpend <= L.tmax * B.t0[b]);
+            }
+        }
+        if (W > 1) {
+            if (tid == 0) sh.ncand = 0;
+            __syncthreads();
+            if (ends) sh.ncand = 1;  // (any thread; benign same-value writes)
+            __syncthreads();
+            ends = uni32(sh.ncand) != 0;
+        }
+        ends = __ballot(ends) != 0;
+        auto block_keyacc = [&](KeyAcc& X) {
+            keyacc_reduce(X);
+            if (W > 1) {
+                if (lane == 0) sh.kacc[wid] = X;
+                __syncthreads();
+                X = sh.kacc[0];
+                for (int w = 1; w < W; ++w) keyacc_merge(X, sh.kacc[w]);
+                __syncthreads();
+                X.f = uni64(X.f); X.m = uni64(X.m); X.ff = uni32(X.ff); X.mh = uni32(X.mh);
+            }
+        };
+        auto block_sum3 = [&](unsigned long long& x0, unsigned long long& x1, unsigned long long& x2) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                x0 += __shfl_xor(x0, off);
+                x1 += __shfl_xor(x1, off);
+                x2 += __shfl_xor(x2, off);
+            }
+            if (W > 1) {
+                if (lane == 0) { sh.sum[wid][0] = x0; sh.sum[wid][1] = x1; sh.sum[wid][2] = x2; }
+                __syncthreads();
+                x0 = 0; x1 = 0; x2 = 0;
+                for (int w = 0; w < W; ++w) { x0 += sh.sum[w][0]; x1 += sh.sum[w][1]; x2 += sh.sum[w][2]; }
+                __syncthreads();
+            }
+            x0 = uni64(x0); x1 = uni64(x1); x2 = uni64(x2);
+        };
+        block_keyacc(P);
+        if ((P.ff & 1u) && ends) {
+            if (tid == 0) atomicAdd(&a_counters[kCntProbe], 1ull);
+            const uint64_t gmin = P.f, gmax = P.m;
+            // ranks of gmin and gmax; unprobed words that hold a key below gmin
+            if (tid == 0) sh.ncand = 0;
+            __syncthreads();
+            unsigned long long rmin = 0, rmax = 0;
+            for (int64_t j = tid; j < words; j += T) {
+                const uint64_t wd = ct.get(j);
+                const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
+                const bool two = kPair && (wd & kPairFlag);
+                const uint64_t k1 = k0 | (1ull << psx);
+                rmin += (k0 < gmin ? 1 : 0) + ((two && k1 < gmin) ? 1 : 0);
+                rmax += (k0 < gmax ? 1 : 0) + ((two && k1 < gmax) ? 1 : 0);
+                const bool probed = j < T || (c1 > 0 && j >= c1);
+                if (!probed && k0 < gmin) {
+                    const unsigned int at = atomicAdd(&sh.ncand, 1u);
+                    if (at < 64) sh.cand[at] = wd;
+                }
+            }
+            __syncthreads();
+            const unsigned int ncand = uni32(sh.ncand);
+            block_sum3(rmin, rmax, nprobe);
+            if (ncand <= 64) {
+                // the candidates (one wavefront checks them)
+                const bool cact = tid < (int)ncand;
+                const uint64_t cw = cact ? sh.cand[tid] : 0;
+                LaneBoxes C;
+                expand(cact, cw, 0, 0, C);
+                check(C);
+                KeyAcc G;
+                keyacc_init(G);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (C.R[b].collide)
+                        keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small, false, -1);
+                unsigned long long ncheck = (C.act[0] ? 1 : 0) + (C.act[1] ? 1 : 0);
+                block_keyacc(G);
+                uint64_t f = gmin;
+                uint32_t ff = P.ff;
+                unsigned long long rf = rmin;
+                if ((G.ff & 1u) && G.f < gmin) {
+                    // a candidate below gmin collides: it is f; its rank by a count
+                    f = G.f;
+                    ff = G.ff;
+                    unsigned long long r = 0, z = 0;
+                    for (int64_t j = tid; j < words; j += T) {
+                        const uint64_t wd = ct.get(j);
+                        const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
+                        const bool two = kPair && (wd & kPairFlag);
+                        r += (k0 < f ? 1 : 0) + ((two && (k0 | (1ull << psx)) < f) ? 1 : 0);
+                    }
+                    block_sum3(r, z, ncheck);
+                    rf = r;
+                } else {
+                    unsigned long long z0 = 0, z1 = 0;
+                    block_sum3(z0, z1, ncheck);
+                }
+                Acc Fa;
+                acc_init(Fa);
+                kc.decode(f, Fa.ft, Fa.fu, Fa.fv);
+                Fa.fflags = ff;
+                Outcome O = decide_first(Fa, S, literal, max_iter, L, rf);
+                if (!O.finish && cap_level && S.N + rmax + 1 >= mI) {
+                    // a colliding box at rank >= m_I - N - 1: the m_I stop
+                    O.finish = true;
+                    O.toi = L.tmax * ((double)Fa.ft * L.wt);
+                    O.tw = L.tmax * L.wt;
+                    O.n = mI;
+                    O.st = kStCap;
+                }
+                if (O.finish) {
+                    if (tid == 0) atomicAdd(&a_counters[kCntProbeHit], 1ull);
+                    early = true;
+                    Oe = O;
+                    checked = nprobe + ncheck;
+                    return;
+                }
+            }
+        }
+    }
+
     uint64_t p0 = 0, p1 = 0, p2 = 0;  // software pipelining: the next chunk loads early
-    if (tid < words) load(tid, p0, p1, p2);
+    if (tid < words) load(0, p0, p1, p2);
     // one chunk of T words: check, accumulate, store the next level; returns
     // whether a colliding box of it could end the query (head try)
     auto chunk = [&](int64_t b0) -> bool {
@@ -1249,8 +1443,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         const bool act = i < words;
         LaneBoxes B;
         expand(act, p0, p1, p2, B);
-        const int64_t inx = i + T;
-        if (inx < words) load(inx, p0, p1, p2);
+        if (i + T < words) load(b0 + T, p0, p1, p2);
         check(B);
         if (kHead) boxes_done += __popcll(__ballot(B.act[0])) + __popcll(__ballot(B.act[1]));
         bool col[2], term[2], e[2], adm[2];
@@ -1342,18 +1535,19 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         for (int b = 0; b < 2; ++b) {
             if (!e[b]) continue;
             if (OP) {
-                if (q[b] < cap) nt[q[b]] = B.key[b] | (adm[b] ? kPairFlag : 0ull);
+                if (q[b] < cap) nt.put(q[b], B.key[b] | (adm[b] ? kPairFlag : 0ull));
             } else {
                 const uint64_t c0t = axis == 0 ? 2 * B.it[b] : B.it[b];
                 const uint64_t c0u = axis == 1 ? 2 * B.iu[b] : B.iu[b];
                 const uint64_t c0v = axis == 2 ? 2 * B.iv[b] : B.iv[b];
                 const int64_t r0 = q[b];
-                if (r0 < cap) { nt[r0] = c0t; nt[cap + r0] = c0u; nt[2 * cap + r0] = c0v; }
+                hbm_u64* nh = nt.hbm;
+                if (r0 < cap) { nh[r0] = c0t; nh[cap + r0] = c0u; nh[2 * cap + r0] = c0v; }
                 const int64_t r1 = r0 + 1;
                 if (adm[b] && r1 < cap) {
-                    nt[r1] = c0t | (axis == 0 ? 1 : 0);
-                    nt[cap + r1] = c0u | (axis == 1 ? 1 : 0);
-                    nt[2 * cap + r1] = c0v | (axis == 2 ? 1 : 0);
+                    nh[r1] = c0t | (axis == 0 ? 1 : 0);
+                    nh[cap + r1] = c0u | (axis == 1 ? 1 : 0);
+                    nh[2 * cap + r1] = c0v | (axis == 2 ? 1 : 0);
                 }
             }
         }
@@ -1389,7 +1583,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
         bool fits = true;
         for (int64_t j0 = done; j0 < words; j0 += T) {
             const int64_t j = j0 + lane;
-            const uint64_t wd = j < words ? ct[j] : 0;
+            const uint64_t wd = j < words ? ct.get(j) : 0;
             const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
             const bool below = j < words && k0 < g;
             const uint64_t m = __ballot(below);
@@ -1422,7 +1616,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
 #pragma unroll
             for (int b = 0; b < 2; ++b) r += (C.act[b] && C.key[b] < f) ? 1 : 0;
             for (int64_t j = lane; j < done; j += T) {
-                const uint64_t wd = ct[j];
+                const uint64_t wd = ct.get(j);
                 if (kPair) {
                     const uint64_t k0 = pair_child(wd, psx, plowx, 0);
                     r += k0 < f ? 1 : 0;
@@ -1487,7 +1681,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const uint64_t* c
 
 // Number of boxes of the level below f and below m (keys as (t, u, v)).
 template <int W, int FIN, int SPLIT>
-__device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct, int64_t cap,
+__device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const Buf& ct, int64_t cap,
                                           const State& S, int64_t words, const Acc& A,
                                           uint64_t& rf, uint64_t& rm) {
     constexpr int T = 64 * W;
@@ -1503,18 +1697,18 @@ __device__ __forceinline__ void rank_pass(GroupShared<W>& sh, const uint64_t* ct
     unsigned long long sf = 0, sm = 0;
     for (int64_t i = tid; i < words; i += T) {
         if (FIN == kFmtPair) {
-            const uint64_t wd = ct[i];
+            const uint64_t wd = ct.get(i);
             const uint64_t k0 = pair_child(wd, psx, plowx, 0);
             const uint64_t k1 = k0 | (1ull << psx);
             const bool two = (wd & kPairFlag) != 0;
             sf += (k0 < fk ? 1 : 0) + ((two && k1 < fk) ? 1 : 0);
             sm += (k0 < mk ? 1 : 0) + ((two && k1 < mk) ? 1 : 0);
         } else if (FIN == kFmtKey) {
-            const uint64_t k = ct[i];
+            const uint64_t k = ct.get(i);
             sf += k < fk ? 1 : 0;
             sm += k < mk ? 1 : 0;
         } else {
-            const uint64_t kt = ct[i], ku = ct[cap + i], kv = ct[2 * cap + i];
+            const uint64_t kt = ct.hbm[i], ku = ct.hbm[cap + i], kv = ct.hbm[2 * cap + i];
             sf += key_less(kt, ku, kv, A.ft, A.fu, A.fv) ? 1 : 0;
             sm += key_less(kt, ku, kv, A.mt, A.mu, A.mv) ? 1 : 0;
         }
@@ -1540,15 +1734,16 @@ __device__ __forceinline__ int depth_sum(const int32_t d[3]) { return d[0] + d[1
 // Dispatch of one level to the pass for its storage format, pair split axis
 // and output format (all wave-uniform).
 template <int W, int KIND>
-__device__ __forceinline__ void run_level(GroupShared<W>& sh, const uint64_t* ct, uint64_t* nt,
+__device__ __forceinline__ void run_level(GroupShared<W>& sh, const Buf& ct, const Buf& nt,
                                           int64_t cap, const State& S, int64_t words, int fmt,
                                           int pa, bool op, const LevelInfo& L, double min_sep,
                                           double delta, bool cap_level, bool literal,
                                           int64_t max_iter, Acc& A, uint64_t& nw, uint64_t& nb,
-                                          bool& early, Outcome& Oe, uint64_t& checked) {
+                                          bool& early, Outcome& Oe, uint64_t& checked,
+                                          unsigned long long* counters) {
 #define CCD_PASS(FIN, SP, OPV)                                                                    \
     level_pass<W, KIND, FIN, SP, OPV>(sh, ct, nt, cap, S, words, L, min_sep, delta, cap_level,    \
-                                      literal, max_iter, A, nw, nb, early, Oe, checked)
+                                      literal, max_iter, A, nw, nb, early, Oe, checked, counters)
     if (fmt == kFmtPair) {
         if (op) {
             if (pa == 0) CCD_PASS(kFmtPair, 0, true);
@@ -1569,7 +1764,7 @@ __device__ __forceinline__ void run_level(GroupShared<W>& sh, const uint64_t* ct
 }
 
 template <int W>
-__device__ __forceinline__ void run_rank(GroupShared<W>& sh, const uint64_t* ct, int64_t cap,
+__device__ __forceinline__ void run_rank(GroupShared<W>& sh, const Buf& ct, int64_t cap,
                                          const State& S, int64_t words, int fmt, int pa,
                                          const Acc& A, uint64_t& rf, uint64_t& rm) {
     if (fmt == kFmtPair) {
@@ -1586,9 +1781,72 @@ __device__ __forceinline__ void run_rank(GroupShared<W>& sh, const uint64_t* ct,
 // The level loop of one query, run by the whole block.  The level's boxes are
 // in buffer 0 of the block's arena when it starts, as packed keys when their
 // depth sum allows it, else as triples.
+// Hands a query on to the next engine at the start of its current level (in
+// buffer ct, `words` words in format fmt): a record with the level's state,
+// its words copied to the hand-off pool.  When the pool is full the record
+// restarts the query at level 0 instead (same results, more work).  Returns
+// false (nothing written) when there is no next engine or no record left.
+template <int W>
+__device__ __forceinline__ bool handoff(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
+                                        const State& S, int fmt, int pa, int64_t words, const Buf& ct,
+                                        int64_t cap, int64_t q) {
+    constexpr int T = 64 * W;
+    const int tid = threadIdx.x;
+    const int64_t nwords = (fmt == kFmtTriple ? 3 : 1) * words;
+    if (tid == 0) {
+        int64_t o = -1, p = -1;
+        if (g.out_records) {
+            const unsigned long long r = atomicAdd(&a.counters[g.out_count_idx], 1ull);
+            if ((int64_t)r < g.out_record_cap) {
+                o = (int64_t)r;
+                const unsigned long long po = atomicAdd(&a.counters[kCntPool], (unsigned long long)nwords);
+                if ((int64_t)po + nwords <= g.out_pool_words) p = (int64_t)po;
+            }
+        }
+        sh.ho[0] = o;
+        sh.ho[1] = p;
+    }
+    __syncthreads();
+    const int64_t o = uni64s(sh.ho[0]), p = uni64s(sh.ho[1]);
+    __syncthreads();  // (sh.ho is not read again before the next level's writes)
+    if (o < 0) return false;
+    uint64_t* orec = g.out_records + o * g.out_record_words;
+    if (p >= 0) {
+        uint64_t* dst = g.out_pool + p;
+        for (int64_t i = tid; i < words; i += T) {
+            if (fmt == kFmtTriple) {
+                dst[i] = ct.hbm[i];
+                dst[words + i] = ct.hbm[cap + i];
+                dst[2 * words + i] = ct.hbm[2 * cap + i];
+            } else {
+                dst[i] = ct.get(i);
+            }
+        }
+    }
+    if (tid == 0) {
+        Record nh;
+        nh.q = q;
+        if (p >= 0) {
+            nh.N = S.N; nh.tpend = S.tpend; nh.wpend = S.wpend; nh.level = S.level;
+            nh.d[0] = S.d[0]; nh.d[1] = S.d[1]; nh.d[2] = S.d[2]; nh.cnt = S.cnt;
+            nh.fmt = (uint32_t)fmt | ((uint32_t)pa << 4);
+            nh.words = (uint64_t)words;
+            orec[kRecordHeaderWords] = (uint64_t)p;
+        } else {
+            nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
+            nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.fmt = kFmtKey; nh.words = 0;
+            orec[kRecordHeaderWords] = 0;
+            atomicAdd(&a.counters[kCntRestart], 1ull);
+        }
+        *reinterpret_cast<Record*>(orec) = nh;
+    }
+    return true;
+}
+
 template <int W, int KIND>
 __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& g, GroupShared<W>& sh,
-                                            uint64_t* base, const Record& h, int fmt, int pa,
+                                            uint64_t* base, uint64_t* lbase, int64_t nl,
+                                            const Record& h, int fmt, int pa,
                                             int64_t words, const double kappa[3],
                                             double delta, double min_sep, double tmax,
                                             int64_t max_iter, bool literal, uint64_t& nchk,
@@ -1606,17 +1864,25 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
         L.axis = (int)uni32((uint32_t)L.axis);
         L.dcap = uni32(L.dcap ? 1u : 0u) != 0;
         L.wt = unif64(L.wt); L.wu = unif64(L.wu); L.wv = unif64(L.wv);
-        const uint64_t* ct = base + cur * 3 * cap;
-        uint64_t* nt = base + (cur ^ 1) * 3 * cap;
         // pairs need this level's keys packed with a spare top bit
         const bool op = fmt != kFmtTriple && depth_sum(S.d) <= 63;
+        const Buf ct{(lds_u64*)(lbase + cur * nl), (hbm_u64*)(base + cur * 3 * cap),
+                     fmt != kFmtTriple ? nl : 0};
+        const Buf nt{(lds_u64*)(lbase + (cur ^ 1) * nl), (hbm_u64*)(base + (cur ^ 1) * 3 * cap),
+                     op ? nl : 0};
+        // the next level could outgrow this arena (it has at most two words per
+        // word of this one): hand the query on before checking this level, so
+        // that the next engine checks it once
+        if (g.out_records && 2 * words > cap &&
+            handoff<W>(a, g, sh, S, fmt, pa, words, ct, cap, h.q))
+            return;
         const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
         Acc A;
         uint64_t nw = 0, nb = 0, checked = 0;
         bool early;
         Outcome Oe;
         run_level<W, KIND>(sh, ct, nt, cap, S, words, fmt, pa, op, L, min_sep, delta, cap_level,
-                           literal, max_iter, A, nw, nb, early, Oe, checked);
+                           literal, max_iter, A, nw, nb, early, Oe, checked, a.counters);
         if (tid == 0) {
             nchk += checked;
             slots += (uint64_t)((words + T - 1) / T) * T * (fmt == kFmtPair ? 2 : 1);
@@ -1633,62 +1899,11 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
             return;
         }
         if (nw > (uint64_t)cap) {
-            // The next level does not fit this engine's arena.  Hand the query
-            // on at the start of this level (fully stored in buffer cur): the
-            // next engine checks the level again and goes on from there.  Its
-            // boxes go to the hand-off pool; when the pool is full the record
-            // restarts the query at level 0 instead (same results, more work).
-            // With no next engine (or no record left) the query ends here with
-            // the flagged overflow return.
-            const int64_t nwords = (fmt == kFmtTriple ? 3 : 1) * words;
-            if (tid == 0) {
-                int64_t o = -1, p = -1;
-                if (g.out_records) {
-                    const unsigned long long r = atomicAdd(&a.counters[g.out_count_idx], 1ull);
-                    if ((int64_t)r < g.out_record_cap) {
-                        o = (int64_t)r;
-                        const unsigned long long po =
-                            atomicAdd(&a.counters[kCntPool], (unsigned long long)nwords);
-                        if ((int64_t)po + nwords <= g.out_pool_words) p = (int64_t)po;
-                    }
-                }
-                sh.ho[0] = o;
-                sh.ho[1] = p;
-            }
-            __syncthreads();
-            const int64_t o = uni64s(sh.ho[0]), p = uni64s(sh.ho[1]);
-            if (o < 0) {
-                if (tid == 0) write_overflow(a, h.q, A, S, L, max_iter);
-                return;
-            }
-            uint64_t* orec = g.out_records + o * g.out_record_words;
-            if (p >= 0) {
-                uint64_t* dst = g.out_pool + p;
-                for (int64_t i = tid; i < words; i += T) {
-                    dst[i] = ct[i];
-                    if (fmt == kFmtTriple) {
-                        dst[words + i] = ct[cap + i];
-                        dst[2 * words + i] = ct[2 * cap + i];
-                    }
-                }
-            }
-            if (tid == 0) {
-                Record nh;
-                nh.q = h.q;
-                if (p >= 0) {
-                    nh.N = S.N; nh.tpend = S.tpend; nh.wpend = S.wpend; nh.level = S.level;
-                    nh.d[0] = S.d[0]; nh.d[1] = S.d[1]; nh.d[2] = S.d[2]; nh.cnt = S.cnt;
-                    nh.fmt = (uint32_t)fmt | ((uint32_t)pa << 4);
-                    nh.words = (uint64_t)words;
-                    orec[kRecordHeaderWords] = (uint64_t)p;
-                } else {
-                    nh.N = 0; nh.tpend = INFINITY; nh.wpend = 0.0; nh.level = 0;
-                    nh.d[0] = nh.d[1] = nh.d[2] = 0; nh.cnt = 1; nh.fmt = kFmtKey; nh.words = 0;
-                    orec[kRecordHeaderWords] = 0;
-                    atomicAdd(&a.counters[kCntRestart], 1ull);
-                }
-                *reinterpret_cast<Record*>(orec) = nh;
-            }
+            // the next level does not fit: hand the query on (it checks this
+            // level again), or end it with the flagged overflow return when
+            // there is no next engine (or no record left)
+            if (!handoff<W>(a, g, sh, S, fmt, pa, words, ct, cap, h.q) && tid == 0)
+                write_overflow(a, h.q, A, S, L, max_iter);
             return;
         }
         // f is colliding and not terminal here, so its word (pairs) or child 0
@@ -1699,11 +1914,16 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
             __syncthreads();
             if (tid == 0) {
                 const int64_t p = A.fpos;
-                const int nwords = op ? 1 : 3;
-                for (int w = 0; w < nwords; ++w) {
-                    const uint64_t x0 = nt[w * cap], xp = nt[w * cap + p];
-                    nt[w * cap] = xp;
-                    nt[w * cap + p] = x0;
+                if (op) {
+                    const uint64_t x0 = nt.get(0), xp = nt.get(p);
+                    nt.put(0, xp);
+                    nt.put(p, x0);
+                } else {
+                    for (int w = 0; w < 3; ++w) {
+                        const uint64_t x0 = nt.hbm[w * cap], xp = nt.hbm[w * cap + p];
+                        nt.hbm[w * cap] = xp;
+                        nt.hbm[w * cap + p] = x0;
+                    }
                 }
             }
         }
@@ -1717,12 +1937,17 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
 }
 
 // OCC: minimum resident waves per SIMD the register allocation must allow.
-template <int W, int OCC>
+// LDS: the first g.lds_words words of every packed level stay in LDS (without
+// it the limit is the constant 0 and the LDS paths compile away).
+template <int W, int OCC, bool LDS>
 __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) {
     constexpr int T = 64 * W;
     const int tid = threadIdx.x;
     __shared__ GroupShared<W> sh;
+    extern __shared__ uint64_t group_lds[];  // two level buffers of g.lds_words words
     const int64_t cap = g.capacity;
+    // (a multiple of T: chunks lie wholly in LDS or wholly in HBM)
+    const int64_t nl = LDS ? (g.lds_words & ~(int64_t)(T - 1)) : 0;
     uint64_t* base = g.arena + (int64_t)blockIdx.x * (6 * cap);
     int64_t in_count = (int64_t)__atomic_load_n(&a.counters[g.in_count_idx], __ATOMIC_RELAXED);
     if (in_count > g.in_record_cap) in_count = g.in_record_cap;
@@ -1763,18 +1988,19 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         int fmt = (int)(h.fmt & 3u), pa = (int)((h.fmt >> 4) & 3u);
         int64_t words = (int64_t)h.words;
         const uint64_t* rb = g.in_pool ? g.in_pool + rec[kRecordHeaderWords] : rec + kRecordHeaderWords;
+        const Buf b0{(lds_u64*)group_lds, (hbm_u64*)base, nl};  // buffer 0, packed formats
         if (h.level == 0 || words > cap || fmt > kFmtTriple) {
             // (words > cap and unknown formats cannot come from the engines
             // before this one; restarting from the root is always correct)
             h.N = 0; h.tpend = INFINITY; h.wpend = 0.0; h.level = 0;
             h.d[0] = h.d[1] = h.d[2] = 0; h.cnt = 1;
             fmt = kFmtKey; pa = 0; words = 1;
-            if (tid == 0) base[0] = 0;
+            if (tid == 0) b0.put(0, 0);
         } else if (fmt == kFmtTriple && depth_sum(h.d) <= 64) {
             KeyCodec kc;
             kc.init(h.d[1], h.d[2]);
             for (int64_t i = tid; i < words; i += T)
-                base[i] = kc.encode(rb[i], rb[words + i], rb[2 * words + i]);
+                b0.put(i, kc.encode(rb[i], rb[words + i], rb[2 * words + i]));
             fmt = kFmtKey;
         } else if (fmt == kFmtTriple) {
             for (int64_t i = tid; i < words; i += T) {
@@ -1783,7 +2009,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
                 base[2 * cap + i] = rb[2 * words + i];
             }
         } else {
-            for (int64_t i = tid; i < words; i += T) base[i] = rb[i];
+            for (int64_t i = tid; i < words; i += T) b0.put(i, rb[i]);
         }
         __syncthreads();
         if (tid < 3) {
@@ -1800,11 +2026,11 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         for (int k = 0; k < 3; ++k) kappa[k] = unif64(kappa[k]);
         __syncthreads();
         if (kind == kEE)
-            group_query<W, kEE>(a, g, sh, base, h, fmt, pa, words, kappa, delta, min_sep, tmax,
-                                max_iter, literal, nchk[1], slots);
+            group_query<W, kEE>(a, g, sh, base, group_lds, nl, h, fmt, pa, words, kappa, delta,
+                                min_sep, tmax, max_iter, literal, nchk[1], slots);
         else
-            group_query<W, kVF>(a, g, sh, base, h, fmt, pa, words, kappa, delta, min_sep, tmax,
-                                max_iter, literal, nchk[0], slots);
+            group_query<W, kVF>(a, g, sh, base, group_lds, nl, h, fmt, pa, words, kappa, delta,
+                                min_sep, tmax, max_iter, literal, nchk[0], slots);
         __syncthreads();
     }
     if (tid == 0) {
@@ -1818,12 +2044,14 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
 // Explicit instantiations used by the runtime.
 template __global__ void k_lane<false>(BatchArgs, LaneCfg);
 template __global__ void k_lane<true>(BatchArgs, LaneCfg);
-template __global__ void k_group<1, 1>(BatchArgs, GroupCfg);
-template __global__ void k_group<1, 2>(BatchArgs, GroupCfg);
-template __global__ void k_group<1, 3>(BatchArgs, GroupCfg);
-template __global__ void k_group<1, 4>(BatchArgs, GroupCfg);
-template __global__ void k_group<2, 1>(BatchArgs, GroupCfg);
-template __global__ void k_group<4, 1>(BatchArgs, GroupCfg);
-template __global__ void k_group<8, 1>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 1, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 2, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 3, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 4, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<2, 1, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<4, 1, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<8, 1, false>(BatchArgs, GroupCfg);
+template __global__ void k_group<1, 3, true>(BatchArgs, GroupCfg);
+template __global__ void k_group<8, 1, true>(BatchArgs, GroupCfg);
 
 }  // namespace ccd

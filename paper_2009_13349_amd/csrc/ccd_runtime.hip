@@ -26,7 +26,7 @@
 namespace ccd {
 template <bool P>
 __global__ void k_lane(BatchArgs a, LaneCfg c);
-template <int W, int OCC>
+template <int W, int OCC, bool LDS>
 __global__ void k_group(BatchArgs a, GroupCfg g);
 __global__ void k_root(BatchArgs a, int64_t* order);
 __global__ void k_min_toi_init(unsigned long long* out);
@@ -82,6 +82,7 @@ void release(DevBuf& b) {
 struct ccd_context {
     int device = 0;
     int num_cu = 256;
+    size_t lds_per_block = 65536;  // device limit of LDS per workgroup
     size_t budget = 0;
     int engine = CCD_ENGINE_PERSISTENT;
     ccd_tuning tune{};
@@ -120,6 +121,8 @@ void default_tuning(ccd_tuning& t, int num_cu) {
     t.group_occupancy = 3;
     t.block_capacity = 0;             // 2 m_I + 2, within the budget
     t.handoff_words = int64_t(1) << 25;  // 256 MiB
+    t.group_lds_words = 0;            // off: measured slower on the simulation-shaped workload
+    t.block_lds_words = 2048;         // 32 KiB per eight-wave block
 }
 
 void clamp_tuning(ccd_tuning& t) {
@@ -136,6 +139,8 @@ void clamp_tuning(ccd_tuning& t) {
     t.group_occupancy = std::min(4, std::max(1, t.group_occupancy));
     t.block_capacity = t.block_capacity <= 0 ? 0 : std::max<int64_t>(256, t.block_capacity);
     t.handoff_words = std::min<int64_t>(int64_t(1) << 34, std::max<int64_t>(0, t.handoff_words));
+    t.group_lds_words = std::min(16384, std::max(0, t.group_lds_words)) & ~63;
+    t.block_lds_words = std::min(16384, std::max(0, t.block_lds_words)) & ~63;
 }
 
 // 0 < t_max <= 1 (false for NaN), no unknown flags.
@@ -291,10 +296,39 @@ Scratch context_scratch(ccd_context* ctx) {
                    (uint64_t*)ctx->group_arena.p, (uint64_t*)ctx->block_arena.p};
 }
 
+// Words of a level kept in LDS by a group-engine kernel: the tuning's value,
+// limited by what the workgroup may hold next to the kernel's static LDS (two
+// buffers of 8-byte words), a multiple of 64.  Kernels that would use more
+// than 64 KiB get the runtime's permission once.
+int64_t group_lds_words(const void* fn, int64_t want, size_t lds_per_block) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, size_t>> seen;  // kernel -> static LDS bytes
+    size_t stat = 32768;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        bool found = false;
+        for (auto& e : seen)
+            if (e.first == fn) { stat = e.second; found = true; }
+        if (!found) {
+            hipFuncAttributes at;
+            if (hipFuncGetAttributes(&at, fn) == hipSuccess) stat = at.sharedSizeBytes;
+            (void)hipGetLastError();
+            seen.emplace_back(fn, stat);
+        }
+    }
+    const size_t room = lds_per_block > stat ? lds_per_block - stat : 0;
+    int64_t w = std::min<int64_t>(want, (int64_t)(room / 16)) & ~int64_t(63);
+    if (w < 0) w = 0;
+    if (w > 0 && 16 * (size_t)w + stat > 65536)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(16 * w));
+    (void)hipGetLastError();
+    return w;
+}
+
 // Issues the batch's kernel sequence on stream s (events ev[0..4] between the
 // kernels when timed).
 void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs a, hipStream_t s,
-             bool persistent, bool timed, hipEvent_t* ev) {
+             bool persistent, bool timed, hipEvent_t* ev, size_t lds_per_block) {
     const int K = tune.lane_capacity;
     a.counters = X.counters;
     a.order = nullptr;
@@ -337,30 +371,36 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     g.out_pool_words = P.pool_words;
     g.out_count_idx = kCntRecB;
     g.tier = 1;
-    switch (tune.group_waves) {
-        case 8:
-            hipLaunchKernelGGL((k_group<8, 1>), dim3(P.group_count), dim3(512), 0, s, a, g);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_group<2, 1>), dim3(P.group_count), dim3(128), 0, s, a, g);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_group<4, 1>), dim3(P.group_count), dim3(256), 0, s, a, g);
-            break;
-        default:
-            switch (tune.group_occupancy) {
-                case 4:
-                    hipLaunchKernelGGL((k_group<1, 4>), dim3(P.group_count), dim3(64), 0, s, a, g);
-                    break;
-                case 3:
-                    hipLaunchKernelGGL((k_group<1, 3>), dim3(P.group_count), dim3(64), 0, s, a, g);
-                    break;
-                case 2:
-                    hipLaunchKernelGGL((k_group<1, 2>), dim3(P.group_count), dim3(64), 0, s, a, g);
-                    break;
-                default:
-                    hipLaunchKernelGGL((k_group<1, 1>), dim3(P.group_count), dim3(64), 0, s, a, g);
-            }
+    {
+        const void* fn;
+        int threads = 64;
+        // levels staged in LDS: the eight-wave and the three-waves-per-SIMD
+        // single-wave kernels have a variant for it
+        const bool lds = tune.group_lds_words > 0 &&
+                         (tune.group_waves == 8 || (tune.group_waves == 1 && tune.group_occupancy == 3));
+        switch (tune.group_waves) {
+            case 8:
+                fn = lds ? (const void*)&k_group<8, 1, true> : (const void*)&k_group<8, 1, false>;
+                threads = 512;
+                break;
+            case 4: fn = (const void*)&k_group<4, 1, false>; threads = 256; break;
+            case 2: fn = (const void*)&k_group<2, 1, false>; threads = 128; break;
+            default:
+                switch (tune.group_occupancy) {
+                    case 4: fn = (const void*)&k_group<1, 4, false>; break;
+                    case 3:
+                        fn = lds ? (const void*)&k_group<1, 3, true> : (const void*)&k_group<1, 3, false>;
+                        break;
+                    case 2: fn = (const void*)&k_group<1, 2, false>; break;
+                    default: fn = (const void*)&k_group<1, 1, false>;
+                }
+        }
+        g.lds_words = lds ? std::min<int64_t>(group_lds_words(fn, tune.group_lds_words, lds_per_block),
+                                              P.group_cap)
+                          : 0;
+        void* args[] = {&a, &g};
+        (void)hipLaunchKernel(fn, dim3(P.group_count), dim3(threads), args,
+                              (size_t)16 * g.lds_words, s);
     }
     if (timed) (void)hipEventRecord(ev[3], s);
 
@@ -380,7 +420,16 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     b.out_pool_words = 0;
     b.out_count_idx = 0;
     b.tier = 2;
-    hipLaunchKernelGGL((k_group<8, 1>), dim3(P.block_count), dim3(512), 0, s, a, b);
+    if (tune.block_lds_words > 0) {
+        b.lds_words = std::min<int64_t>(
+            group_lds_words((const void*)&k_group<8, 1, true>, tune.block_lds_words, lds_per_block),
+            P.block_cap);
+        hipLaunchKernelGGL((k_group<8, 1, true>), dim3(P.block_count), dim3(512),
+                           (size_t)16 * b.lds_words, s, a, b);
+    } else {
+        b.lds_words = 0;
+        hipLaunchKernelGGL((k_group<8, 1, false>), dim3(P.block_count), dim3(512), 0, s, a, b);
+    }
     if (timed) (void)hipEventRecord(ev[4], s);
 }
 
@@ -427,7 +476,7 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
                              "hipStreamBeginCapture");
             if (ok) {
                 enqueue(ctx->tune, P, context_scratch(ctx), a, ctx->cap_stream, persistent, timed,
-                        ctx->ev);
+                        ctx->ev, ctx->lds_per_block);
                 hipGraph_t g = nullptr;
                 ok = hip_ok(hipStreamEndCapture(ctx->cap_stream, &g), "hipStreamEndCapture");
                 if (ok) {
@@ -448,7 +497,7 @@ int launch(ccd_context* ctx, const Plan& P, BatchArgs a, hipStream_t s, bool per
         }
         return hip_ok(hipGraphLaunch(ctx->graph_exec, s), "hipGraphLaunch") ? CCD_OK : CCD_EDEVICE;
     }
-    enqueue(ctx->tune, P, context_scratch(ctx), a, s, persistent, timed, ctx->ev);
+    enqueue(ctx->tune, P, context_scratch(ctx), a, s, persistent, timed, ctx->ev, ctx->lds_per_block);
     return hip_ok(hipGetLastError(), "kernel launch") ? CCD_OK : CCD_EDEVICE;
 }
 
@@ -569,8 +618,10 @@ int ccd_context_create(int device, size_t mem_budget_bytes, ccd_context** out) {
     c->device = device;
     c->budget = mem_budget_bytes ? mem_budget_bytes : ((size_t)16 << 30);
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
         c->num_cu = prop.multiProcessorCount;
+        if (prop.sharedMemPerBlock >= 16384) c->lds_per_block = prop.sharedMemPerBlock;
+    }
     default_tuning(c->tune, c->num_cu);
     c->have_events = true;
     for (int i = 0; i < 5; ++i)
@@ -618,6 +669,8 @@ int ccd_plan_scratch(const ccd_tuning* tuning, int num_cu, size_t mem_budget_byt
         if (u->group_occupancy) n2.group_occupancy = u->group_occupancy;
         if (u->block_capacity) n2.block_capacity = u->block_capacity < 0 ? 0 : u->block_capacity;
         if (u->handoff_words) n2.handoff_words = u->handoff_words < 0 ? 0 : u->handoff_words;
+        if (u->group_lds_words) n2.group_lds_words = u->group_lds_words < 0 ? 0 : u->group_lds_words;
+        if (u->block_lds_words) n2.block_lds_words = u->block_lds_words < 0 ? 0 : u->block_lds_words;
         clamp_tuning(n2);
         t = n2;
     }
@@ -662,6 +715,8 @@ int ccd_context_set_tuning(ccd_context* c, const ccd_tuning* t) {
     if (t->group_occupancy) n.group_occupancy = t->group_occupancy;
     if (t->block_capacity) n.block_capacity = t->block_capacity < 0 ? 0 : t->block_capacity;
     if (t->handoff_words) n.handoff_words = t->handoff_words < 0 ? 0 : t->handoff_words;
+    if (t->group_lds_words) n.group_lds_words = t->group_lds_words < 0 ? 0 : t->group_lds_words;
+    if (t->block_lds_words) n.block_lds_words = t->block_lds_words < 0 ? 0 : t->block_lds_words;
     clamp_tuning(n);
     c->tune = n;
     return CCD_OK;
@@ -705,6 +760,8 @@ int ccd_context_last_stats(ccd_context* c, ccd_stats* out) {
     out->restarted = h[kCntRestart];
     out->deep = h[kCntDeep];
     out->handoff_words = h[kCntPool];
+    out->probes[0] = h[kCntProbe];
+    out->probes[1] = h[kCntProbeHit];
     if (c->last_timed)
         for (int i = 0; i < 4; ++i)
             if (!hip_ok(hipEventElapsedTime(&out->kernel_ms[i], c->ev[i], c->ev[i + 1]),
@@ -946,7 +1003,7 @@ extern "C" int ccd_batch_noalloc(ccd_context* ctx, const ccd_batch_desc* d, cons
     // counters and graph are not touched, so ccd_context_last_stats does not
     // describe this call
     ctx->last_valid = false;
-    enqueue(ctx->tune, P, X, a, (hipStream_t)stream, persistent, false, nullptr);
+    enqueue(ctx->tune, P, X, a, (hipStream_t)stream, persistent, false, nullptr, ctx->lds_per_block);
     return hip_ok(hipGetLastError(), "ccd_batch_noalloc launch") ? CCD_OK : CCD_EDEVICE;
 }
 
@@ -1009,6 +1066,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
         {2, {8, 16, 32}},          // lane_capacity
         {3, {4, 8, 12}},           // lane_waves_per_cu
         {4, {1, 2}},               // group_waves
+        {5, {0, 256, 512}},        // group_lds_words
     };
     for (int pass = 0; pass < 2 && rc == CCD_OK; ++pass) {
         bool improved = false;
@@ -1024,6 +1082,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
                     case 4: t.group_waves = (int32_t)v;
                             t.group_count = (int32_t)(v == 1 ? 4 * cu * t.group_occupancy : 4 * cu * 2 / v);
                             break;
+                    case 5: t.group_lds_words = (int32_t)v; break;
                 }
                 clamp_tuning(t);
                 if (std::memcmp(&t, &best, sizeof(t)) == 0) continue;
@@ -1065,7 +1124,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
 }
 
 // Tuning cache: one line per (device, workload key):
-//   <arch> <cus> <hip-version> <key> <the ten ccd_tuning fields>
+//   <arch> <cus> <hip-version> <key> <the twelve ccd_tuning fields>
 namespace {
 void device_tag(ccd_context* ctx, char* arch, size_t n, int* hipver) {
     hipDeviceProp_t prop;
@@ -1102,10 +1161,11 @@ int ccd_tuning_cache_store(ccd_context* ctx, const char* path, const char* key) 
     if (!f) return CCD_EINVAL;
     for (const std::string& l : keep) std::fputs(l.c_str(), f);
     const ccd_tuning& t = ctx->tune;
-    std::fprintf(f, "%s %d %d %s %d %d %lld %d %d %lld %d %d %lld %lld\n", arch, ctx->num_cu, ver,
-                 key, t.lane_waves_per_cu, t.lane_capacity, (long long)t.lane_budget, t.group_waves,
-                 t.group_count, (long long)t.group_capacity, t.block_count, t.group_occupancy,
-                 (long long)t.block_capacity, (long long)t.handoff_words);
+    std::fprintf(f, "%s %d %d %s %d %d %lld %d %d %lld %d %d %lld %lld %d %d\n", arch, ctx->num_cu,
+                 ver, key, t.lane_waves_per_cu, t.lane_capacity, (long long)t.lane_budget,
+                 t.group_waves, t.group_count, (long long)t.group_capacity, t.block_count,
+                 t.group_occupancy, (long long)t.block_capacity, (long long)t.handoff_words,
+                 t.group_lds_words, t.block_lds_words);
     std::fclose(f);
     return CCD_OK;
 }
@@ -1125,9 +1185,10 @@ int ccd_tuning_cache_load(ccd_context* ctx, const char* path, const char* key) {
         int c, v;
         long long lb, gc, bc, hw;
         ccd_tuning r{};
-        if (std::sscanf(line, "%127s %d %d %127s %d %d %lld %d %d %lld %d %d %lld %lld", a, &c, &v, k,
-                        &r.lane_waves_per_cu, &r.lane_capacity, &lb, &r.group_waves, &r.group_count,
-                        &gc, &r.block_count, &r.group_occupancy, &bc, &hw) == 14 &&
+        if (std::sscanf(line, "%127s %d %d %127s %d %d %lld %d %d %lld %d %d %lld %lld %d %d", a, &c,
+                        &v, k, &r.lane_waves_per_cu, &r.lane_capacity, &lb, &r.group_waves,
+                        &r.group_count, &gc, &r.block_count, &r.group_occupancy, &bc, &hw,
+                        &r.group_lds_words, &r.block_lds_words) == 16 &&
             std::strcmp(a, arch) == 0 && c == ctx->num_cu && v == ver && std::strcmp(k, key) == 0) {
             r.lane_budget = lb;
             r.group_capacity = gc;

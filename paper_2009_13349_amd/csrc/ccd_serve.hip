@@ -143,7 +143,9 @@ struct ResultLayout {
 struct Slot {
     ccd_context* ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipEvent_t start = nullptr;  // device time of a launch: start -> done
     hipEvent_t done = nullptr;
+    int64_t queries = 0;         // queries of the launch in flight
     ReqEntry* d_table = nullptr;
     ReqEntry* h_table = nullptr;  // pinned
     std::vector<Request*> reqs;
@@ -167,6 +169,7 @@ struct ccd_server {
     std::map<int64_t, Request*> tickets;
     std::vector<hipEvent_t> event_pool;
     int64_t next_ticket = 1;
+    double ms_per_query = 0.0;  // device time per query of recent launches (EWMA; 0: none yet)
     bool stop = false;
     bool failed = false;
     std::thread worker;
@@ -257,9 +260,14 @@ void admit(ccd_server* s) {
 void launch_slot(ccd_server* s, Slot& sl) {
     std::vector<Request*> take;
     int64_t total = 0, mi_max = 1;
+    // latency bound: as many queries as fill the target device time at the
+    // measured cost per query (the first request always goes)
+    int64_t limit = s->cfg.max_queries_per_launch;
+    if (s->cfg.launch_target_us > 0 && s->ms_per_query > 0.0)
+        limit = std::min<int64_t>(limit, (int64_t)(1e-3 * s->cfg.launch_target_us / s->ms_per_query) + 1);
     while (!s->ready.empty() && (int)take.size() < s->cfg.max_requests) {
         Request* r = s->ready.front();
-        if (!take.empty() && total + r->n > s->cfg.max_queries_per_launch) break;
+        if (!take.empty() && total + r->n > limit) break;
         s->ready.pop_front();
         take.push_back(r);
         total += r->n;
@@ -292,6 +300,8 @@ void launch_slot(ccd_server* s, Slot& sl) {
     }
     ok = ok && record_hip(hipMemcpyAsync(sl.d_table, sl.h_table, take.size() * sizeof(ReqEntry),
                                          hipMemcpyHostToDevice, sl.stream), "serve copy table");
+    ok = ok && record_hip(hipEventRecord(sl.start, sl.stream), "serve event");
+    sl.queries = total;
     BatchArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n = total;
@@ -335,6 +345,15 @@ void worker_main(ccd_server* s) {
             std::vector<Request*> reqs = std::move(sl.reqs);
             sl.reqs.clear();
             sl.busy = false;
+            float ms = 0.0f;
+            if (rc == CCD_OK && sl.queries > 0 &&
+                hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess && ms > 0.0f) {
+                // (launches on two streams overlap, so this is the time a launch
+                // takes next to another one: the latency it sees)
+                const double c = (double)ms / (double)sl.queries;
+                s->ms_per_query = s->ms_per_query > 0.0 ? 0.8 * s->ms_per_query + 0.2 * c : c;
+            }
+            (void)hipGetLastError();
             if (rc == CCD_OK) {
                 lk.unlock();
                 for (Request* r : reqs) {
@@ -390,6 +409,7 @@ void destroy(ccd_server* s) {
     for (Slot& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.start) (void)hipEventDestroy(sl.start);
         if (sl.d_table) (void)hipFree(sl.d_table);
         if (sl.h_table) (void)hipHostFree(sl.h_table);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -421,6 +441,7 @@ void ccd_serve_config_default(ccd_serve_config* c) {
     c->streams = 2;
     c->max_requests = 1024;
     c->max_queries_per_launch = 4000000;
+    c->launch_target_us = 5000;
     c->pool_bytes = (size_t)8 << 30;
     c->scratch_bytes = (size_t)12 << 30;
 }
@@ -431,7 +452,7 @@ int ccd_serve_open(const ccd_serve_config* cfg, ccd_server** out) {
     ccd_serve_config_default(&c);
     if (cfg) c = *cfg;
     if (c.streams < 1 || c.streams > 4 || c.max_requests < 1 || c.max_queries_per_launch < 1 ||
-        c.pool_bytes < 4096)
+        c.pool_bytes < 4096 || c.launch_target_us < 0)
         return CCD_EINVAL;
     ccd_server* s = new ccd_server();
     s->cfg = c;
@@ -463,7 +484,8 @@ int ccd_serve_open(const ccd_serve_config* cfg, ccd_server** out) {
             return rc;
         }
         if (!record_hip(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking), "serve stream") ||
-            !record_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "serve event") ||
+            !record_hip(hipEventCreate(&sl.start), "serve event") ||
+            !record_hip(hipEventCreate(&sl.done), "serve event") ||
             !record_hip(hipMalloc((void**)&sl.d_table, sizeof(ReqEntry) * c.max_requests), "serve table") ||
             !record_hip(hipHostMalloc((void**)&sl.h_table, sizeof(ReqEntry) * c.max_requests, 0), "serve table")) {
             destroy(s);

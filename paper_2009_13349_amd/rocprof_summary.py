@@ -2,7 +2,9 @@
 
     python -m paper_2009_13349_amd.rocprof_summary stats <kernel_stats.csv>
     python -m paper_2009_13349_amd.rocprof_summary traffic <fetch_counter_collection.csv> \
-        <write_counter_collection.csv> [--copy-bytes N]
+        <write_counter_collection.csv> [--copy-bytes N] [--tuning k=v,...]
+    python -m paper_2009_13349_amd.rocprof_summary counters <counter_collection.csv>... \
+        [--tuning k=v,...]
 
 `stats` prints the per-kernel duration table of a --kernel-trace --stats run.
 `traffic` prints per-dispatch HBM bytes of FETCH_SIZE and WRITE_SIZE runs
@@ -10,6 +12,9 @@
 size to what the same counter read for it (the largest __amd_rocclr_copyBuffer
 dispatch), and writes a JSON record of the scaled figures keyed by the
 SHA-256 of the kernel sources they were taken with.
+`counters` prints and records (same keying) the per-dispatch mean of every
+counter in the given --pmc runs, per CCD kernel.  With --tuning the records
+also carry the ccd_tuning the profiled run used.
 """
 from __future__ import annotations
 
@@ -80,6 +85,33 @@ def traffic(fetch_path: str, write_path: str, copy_bytes: int = 256 << 20):
     return "\n".join(out), rec
 
 
+def counters(paths):
+    """Per-dispatch means of every counter of the CCD kernels over --pmc runs."""
+    agg = defaultdict(lambda: defaultdict(list))
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if not name.startswith(("void ccd", "ccd")):
+                continue
+            agg[short(name)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    rec = {"kernel_source_sha256": kernel_source_hash(), "kernels": {}}
+    out = ["| kernel | counter | dispatches | per dispatch |", "|---|---|---|---|"]
+    for k in sorted(agg):
+        rec["kernels"][k] = {}
+        for c in sorted(agg[k]):
+            v = agg[k][c]
+            rec["kernels"][k][c] = sum(v) / len(v)
+            out.append(f"| `{k}` | {c} | {len(v)} | {sum(v) / len(v):.4g} |")
+    return "\n".join(out), rec
+
+
+def _tuning(argv):
+    if "--tuning" not in argv:
+        return None
+    kv = argv[argv.index("--tuning") + 1]
+    return {k: int(v) for k, v in (x.split("=") for x in kv.split(",") if x)}
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats(argv[1]))
@@ -88,6 +120,14 @@ def main(argv):
         if "--copy-bytes" in argv:
             copy_bytes = int(argv[argv.index("--copy-bytes") + 1])
         table, rec = traffic(argv[1], argv[2], copy_bytes)
+        rec["tuning"] = _tuning(argv)
+        print(table)
+        print()
+        print(json.dumps(rec))
+    elif argv[0] == "counters":
+        paths = argv[1:argv.index("--tuning")] if "--tuning" in argv else argv[1:]
+        table, rec = counters(paths)
+        rec["tuning"] = _tuning(argv)
         print(table)
         print()
         print(json.dumps(rec))

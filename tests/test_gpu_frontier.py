@@ -100,3 +100,23 @@ def test_lane_capacities(ctx, torch_dev, cap):
     for engine in (0, 1):
         got = run_gpu(ctx, torch_dev, w, engine, max_iter=100_000)
         assert_same(got, ref, what=f"lane capacity {cap}, engine {engine}")
+
+
+@pytest.mark.parametrize("tune", [
+    {"group_lds_words": 64},                       # levels of more than one chunk spill to HBM
+    {"group_lds_words": 512},
+    {"group_lds_words": 512, "group_capacity": 256, "block_lds_words": 64},
+    {"group_lds_words": 0, "group_capacity": 256, "block_lds_words": 4096},
+    {"group_lds_words": 512, "group_waves": 8},
+    {"group_lds_words": 512, "group_occupancy": 2},  # no LDS variant: plain HBM arena
+])
+def test_group_levels_staged_in_lds(ctx, torch_dev, wide, tune):
+    """The first words of every level in LDS, the rest in the HBM arena, at
+    sizes that make most levels straddle the boundary, in the group and the
+    block engine (with the lane engine handing everything on)."""
+    w, ref = wide
+    ctx.set_tuning(lane_capacity=8, lane_budget=1, **tune)
+    for engine in (0, 1):
+        got = run_gpu(ctx, torch_dev, w, engine)
+        assert_same(got, ref, what=f"LDS-staged levels {tune}, engine {engine}")
+        assert ctx.last_stats()["overflowed"] == 0

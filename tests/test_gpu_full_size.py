@@ -1,0 +1,77 @@
+"""GPU <-> oracle parity at full size, in the launch configuration the
+benchmark times: the 100,000-query edge-edge workload, the 1,000,000-query
+simulation-shaped workload and the four 1,000,000-query minimum-separation
+runs, each solved in one ccd_batch call on the GPU.
+
+The oracle cannot replay these sets in a test's time (a capped query costs it
+about half a second), so tests/golden/make_full_size.py (oracle only) stored,
+for each selection, a SHA-256 digest of the oracle's five result arrays over
+the selected queries in index order, plus a few results in clear.  Selected:
+every degenerate edge-edge query (parallel, coplanar, touching at t = 0 or
+t = 1, static, endpoint-on-edge: the cap-hitting tail), every near-contact and
+grazing simulation-shaped query, and stratified samples of the
+minimum-separation runs and of the generic queries.  The GPU's results on the
+same indices must have the same digest: every field bit-identical."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_13349_amd import workloads as W
+
+from test_gpu_parity import FIELDS, ccdmod, ctx, run_gpu, torch_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_size_oracle.json")
+
+
+def digest(r: dict) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(r["toi"], dtype=np.float64).view(np.uint64).tobytes())
+    h.update(np.ascontiguousarray(r["t_width"], dtype=np.float64).view(np.uint64).tobytes())
+    h.update(np.ascontiguousarray(r["n_checks"]).astype(np.uint64).tobytes())
+    h.update(np.ascontiguousarray(r["hit"]).astype(np.uint8).tobytes())
+    h.update(np.ascontiguousarray(r["status"]).astype(np.uint8).tobytes())
+    return h.hexdigest()
+
+
+def _cases():
+    data = json.load(open(GOLDEN))
+    groups = {}
+    for c in data["cases"]:
+        key = (json.dumps(c["workload"], sort_keys=True), c["delta"], c["min_sep"])
+        groups.setdefault(key, []).append(c)
+    return data["max_iter"], list(groups.items())
+
+
+MAX_ITER, GROUPS = _cases() if os.path.exists(GOLDEN) else (0, [])
+
+
+@pytest.mark.parametrize("key,cases", GROUPS, ids=[f"{c[0]['name']}" for _, c in GROUPS])
+def test_full_size_against_oracle_digests(ctx, torch_dev, key, cases):
+    spec = cases[0]["workload"]
+    w = getattr(W, spec["fn"])(**spec["args"])
+    assert w["name"] == cases[0]["name"]
+    got = run_gpu(ctx, torch_dev, w, 0, delta=cases[0]["delta"], max_iter=MAX_ITER,
+                  min_sep=cases[0]["min_sep"])
+    assert ctx.last_stats()["overflowed"] == 0
+    for c in cases:
+        if c["indices"] is None:
+            cls = c["class"] if isinstance(c["class"], list) else [c["class"]]
+            idx = np.nonzero(np.isin(w["cls"], cls))[0]
+        else:
+            idx = np.asarray(c["indices"], dtype=np.int64)
+        assert len(idx) == c["count"]
+        sub = {k: got[k][idx] for k in FIELDS}
+        what = f"{c['name']} class {c['class']} ({c['count']} queries)"
+        for s in c["sample"]:
+            q = s["q"]
+            assert (float(got["toi"][q]).hex(), float(got["t_width"][q]).hex(), int(got["n_checks"][q]),
+                    int(got["hit"][q]), int(got["status"][q])) == \
+                (s["toi"], s["t_width"], s["n_checks"], s["hit"], s["status"]), f"{what}: query {q}"
+        assert int(sub["hit"].sum()) == c["hits"], what
+        assert int(np.count_nonzero(sub["status"] & 1)) == c["capped"], what
+        assert digest(sub) == c["sha256"], f"{what}: results differ from the oracle's"
