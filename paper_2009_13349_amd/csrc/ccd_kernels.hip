@@ -1054,7 +1054,16 @@ struct GroupShared {
 //
 // tv, uv, vv: the box's lower and upper ends per axis; on the split axis SPLIT
 // three values lo < mid < hi (child 0 = [lo, mid], child 1 = [mid, hi]).
-template <int KIND, int SPLIT>
+//
+// Edge-edge corners: F = fl(ea_b - eb_e) with ea_b depending only on the u end
+// b and eb_e only on the v end e (for a time plane).  Rounding is monotonic
+// (x <= y implies fl(x) <= fl(y)), so over any set of corners that is a
+// product of u ends and v ends, min F = fl(min ea - max eb) and max F =
+// fl(max ea - min eb): the same values as the corner-by-corner minimum and
+// maximum (up to the sign of a zero, which no comparison or width below can
+// see), with fewer operations.  MS: the enlargement by d is applied only
+// with d > 0 (x - 0 = x exactly).
+template <int KIND, int SPLIT, bool MS>
 __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* Es,
                                                const double tv[3], const double uv[3],
                                                const double vv[3], double min_sep, double delta,
@@ -1084,6 +1093,31 @@ __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* E
                 for (int b = 0; b < NB; ++b) ea[b] = (1.0 - uv[b]) * P[0] + uv[b] * P[1];
 #pragma unroll
                 for (int e = 0; e < NE; ++e) eb[e] = (1.0 - vv[e]) * P[2] + vv[e] * P[3];
+                double lo[3], hi[3];
+                int ng;
+                if (SPLIT == 0) {
+                    const double mna = fmin(ea[0], ea[1]), mxa = fmax(ea[0], ea[1]);
+                    const double mnb = fmin(eb[0], eb[1]), mxb = fmax(eb[0], eb[1]);
+                    lo[0] = mna - mxb; hi[0] = mxa - mnb; ng = 1;
+                } else if (SPLIT == 1) {
+                    const double mnb = fmin(eb[0], eb[1]), mxb = fmax(eb[0], eb[1]);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) { lo[b] = ea[b] - mxb; hi[b] = ea[b] - mnb; }
+                    ng = NB;
+                } else {
+                    const double mna = fmin(ea[0], ea[1]), mxa = fmax(ea[0], ea[1]);
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) { lo[e] = mna - eb[e]; hi[e] = mxa - eb[e]; }
+                    ng = NE;
+                }
+#pragma unroll
+                for (int g = 0; g < 3; ++g) {
+                    if (g >= ng) break;
+                    const int sp = SPLIT == 0 ? a : g;
+                    if (!gset[sp]) { glo[sp] = lo[g]; ghi[sp] = hi[g]; gset[sp] = true; }
+                    else { glo[sp] = fmin(glo[sp], lo[g]); ghi[sp] = fmax(ghi[sp], hi[g]); }
+                }
+                continue;
             }
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -1112,13 +1146,13 @@ __device__ __forceinline__ void check_pair_lds(const double* Xs, const double* E
         const double lo1 = fmin(glo[1], glo[2]), hi1 = fmax(ghi[1], ghi[2]);
         const double eps = Es[c];
         {
-            const double l = lo0 - min_sep, h = hi0 + min_sep;
+            const double l = MS ? lo0 - min_sep : lo0, h = MS ? hi0 + min_sep : hi0;
             col0 = col0 && (l <= eps) && (h >= -eps);
             ins0 = ins0 && (l >= -eps) && (h <= eps);
             wid0 = fmax(wid0, hi0 - lo0);
         }
         {
-            const double l = lo1 - min_sep, h = hi1 + min_sep;
+            const double l = MS ? lo1 - min_sep : lo1, h = MS ? hi1 + min_sep : hi1;
             col1 = col1 && (l <= eps) && (h >= -eps);
             ins1 = ins1 && (l >= -eps) && (h <= eps);
             wid1 = fmax(wid1, hi1 - lo1);
@@ -1267,8 +1301,12 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
             tv[2] = L.tmax * ((B.t0[0] + L.wt) + L.wt);
             uv[0] = B.u0[0]; uv[1] = uv[0] + L.wu; uv[2] = uv[1] + L.wu;
             vv[0] = B.v0[0]; vv[1] = vv[0] + L.wv; vv[2] = vv[1] + L.wv;
-            check_pair_lds<KIND, SPLIT>(sh.Xs, sh.Es, tv, uv, vv, min_sep, delta, B.act[1],
-                                        B.R[0], B.R[1]);
+            if (min_sep > 0.0)
+                check_pair_lds<KIND, SPLIT, true>(sh.Xs, sh.Es, tv, uv, vv, min_sep, delta, B.act[1],
+                                                  B.R[0], B.R[1]);
+            else
+                check_pair_lds<KIND, SPLIT, false>(sh.Xs, sh.Es, tv, uv, vv, min_sep, delta, B.act[1],
+                                                   B.R[0], B.R[1]);
         } else {
             B.R[0] = check_box_lds<KIND>(sh.Xs, sh.Es, L.tmax * B.t0[0], L.tmax * (B.t0[0] + L.wt), B.u0[0],
                                          B.u0[0] + L.wu, B.v0[0], B.v0[0] + L.wv, min_sep, delta);
