@@ -1005,6 +1005,7 @@ constexpr uint64_t kPairFlag = 1ull << 63;  // the pair's child 1 passed the pri
 // LDS access and a global access apart instead of merging them into one flat
 // access through a selected pointer.)
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
+constexpr int kProbeChunks = 16;  // level probe: leading chunks scanned for a colliding box
 typedef __attribute__((address_space(1))) uint64_t hbm_u64;
 
 struct Buf {
@@ -1034,7 +1035,7 @@ struct GroupShared {
     unsigned long long next_box;  // W > 1: boxes of the next level
     int64_t rec;
     int64_t ho[2];      // hand-off: record index and pool offset (or -1)
-    uint64_t cand[64];  // head try: unchecked words below the running first colliding key
+    uint64_t cand[64 * W];  // head try / level probe: unchecked words below the first colliding key
     unsigned int ncand; // cap-level probe: candidates gathered
 };
 
@@ -1320,25 +1321,27 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
     // m_I - N - 1, with t_lo(f) either way; only when neither happens does the
     // level go on to the next.  So f with its rank, and on such a level any
     // colliding box of large enough rank, decide the level without checking
-    // the boxes in between.  When the level's first chunk (which holds its
-    // smallest key) shows a colliding box that could end the query, or on an
-    // m_I level, the probe checks that chunk and (m_I level) the last one
-    // (keys of large rank), counts ranks with one pass over the keys, checks
-    // the unprobed boxes below the smallest colliding probe box (so that f is
-    // exact), and returns the decision if it is proven; otherwise the level is
-    // checked in full as usual.  (Single-wave groups stop the same levels
-    // with the head try below; measured, a probe there costs more in register
-    // pressure than it saves.)
+    // the boxes in between.  The probe checks the level's chunks in storage
+    // order (the first holds its smallest key) until one holds a colliding
+    // box, and on an m_I level also the last chunk (keys of large rank).
+    // When a checked colliding box could end the query (terminal, at or after
+    // the carried box), or on an m_I level, it counts ranks with one pass over
+    // the keys, checks the unprobed boxes below the smallest colliding probe
+    // box (so that f is exact), and returns the decision if it is proven;
+    // otherwise the level is checked in full as usual.  (Single-wave groups
+    // stop the same levels with the head try below, and hand m_I levels of
+    // more than four chunks to the block tier; measured, a probe there costs
+    // more in register pressure than it saves.)
     if (kPacked && W > 1) {
         const uint64_t mI = (uint64_t)max_iter;
-        const int64_t c1 = (cap_level && words > T) ? ((words - 1) / T) * T : 0;  // last chunk
         KeyAcc P;
         keyacc_init(P);
         unsigned long long nprobe = 0;
         bool ends = cap_level;
-        for (int pc = 0; pc < 2; ++pc) {
-            const int64_t c = pc == 0 ? 0 : c1;
-            if (pc == 1 && c1 == 0) break;
+        // the level's first chunks, in storage order, until one holds a
+        // colliding box (at most kProbeChunks of them), then (m_I level) the
+        // last chunk
+        auto probe_chunk = [&](int64_t c) -> bool {
             uint64_t q0 = 0, q1 = 0, q2 = 0;
             const bool act = c + tid < words;
             if (act) load(c, q0, q1, q2);
@@ -1346,22 +1349,35 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
             expand(act, q0, q1, q2, B);
             check(B);
             nprobe += (B.act[0] ? 1 : 0) + (B.act[1] ? 1 : 0);
+            bool col = false;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 if (!B.R[b].collide) continue;
+                col = true;
                 const bool tb = B.R[b].small || L.dcap;
                 keyacc_add(P, B.key[b], B.it[b], tb, B.R[b].small, true, -1);
                 ends = ends || tb || (!literal && S.tpend <= L.tmax * B.t0[b]);
             }
+            return col;
+        };
+        int64_t cend = 0;  // chunks [0, cend) scanned
+        for (int k = 0; k < kProbeChunks && cend < words; ++k) {
+            const bool col = probe_chunk(cend);
+            cend += T;
+            if (__syncthreads_or(col ? 1 : 0)) break;
         }
-        if (W > 1) {
-            if (tid == 0) sh.ncand = 0;
-            __syncthreads();
-            if (ends) sh.ncand = 1;  // (any thread; benign same-value writes)
-            __syncthreads();
-            ends = uni32(sh.ncand) != 0;
+        // m_I level: the last chunks, backwards, until one holds a colliding box
+        // (at most kProbeChunks of them, none already scanned): [c1, words)
+        int64_t c1 = words;
+        if (cap_level) {
+            int64_t c = ((words - 1) / T) * T;
+            for (int k = 0; k < kProbeChunks && c >= cend; ++k, c -= T) {
+                const bool col = probe_chunk(c);
+                c1 = c;
+                if (__syncthreads_or(col ? 1 : 0)) break;
+            }
         }
-        ends = __ballot(ends) != 0;
+        ends = __syncthreads_or(ends ? 1 : 0) != 0;
         auto block_keyacc = [&](KeyAcc& X) {
             keyacc_reduce(X);
             if (W > 1) {
@@ -1404,17 +1420,17 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
                 const uint64_t k1 = k0 | (1ull << psx);
                 rmin += (k0 < gmin ? 1 : 0) + ((two && k1 < gmin) ? 1 : 0);
                 rmax += (k0 < gmax ? 1 : 0) + ((two && k1 < gmax) ? 1 : 0);
-                const bool probed = j < T || (c1 > 0 && j >= c1);
+                const bool probed = j < cend || j >= c1;
                 if (!probed && k0 < gmin) {
                     const unsigned int at = atomicAdd(&sh.ncand, 1u);
-                    if (at < 64) sh.cand[at] = wd;
+                    if (at < (unsigned int)T) sh.cand[at] = wd;
                 }
             }
             __syncthreads();
             const unsigned int ncand = uni32(sh.ncand);
             block_sum3(rmin, rmax, nprobe);
-            if (ncand <= 64) {
-                // the candidates (one wavefront checks them)
+            if (ncand <= (unsigned int)T) {
+                // the candidates (one chunk's worth, one per thread)
                 const bool cact = tid < (int)ncand;
                 const uint64_t cw = cact ? sh.cand[tid] : 0;
                 LaneBoxes C;
@@ -1908,13 +1924,15 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
                      fmt != kFmtTriple ? nl : 0};
         const Buf nt{(lds_u64*)(lbase + (cur ^ 1) * nl), (hbm_u64*)(base + (cur ^ 1) * 3 * cap),
                      op ? nl : 0};
+        const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
         // the next level could outgrow this arena (it has at most two words per
-        // word of this one): hand the query on before checking this level, so
-        // that the next engine checks it once
-        if (g.out_records && 2 * words > cap &&
+        // word of this one), or this is a level where m_I can stop the query and
+        // it spans more than a few chunks (the next engine's level probe
+        // decides such a level without checking it in full): hand the query on
+        // before checking this level, so that the next engine checks it once
+        if (g.out_records && (2 * words > cap || (cap_level && words > 4 * T)) &&
             handoff<W>(a, g, sh, S, fmt, pa, words, ct, cap, h.q))
             return;
-        const bool cap_level = S.N + S.cnt >= (uint64_t)max_iter;
         Acc A;
         uint64_t nw = 0, nb = 0, checked = 0;
         bool early;
