@@ -306,7 +306,8 @@ def measure_workload(ctx, torch, w, steps, warmup):
            "steps": steps, "delta": w["delta"], "max_iter": w["max_iter"], "min_sep": w["min_sep"],
            "hits": int(out.hit.sum().item()),
            "capped": int(((out.status & 1) != 0).sum().item()),
-           "overflowed": stats[-1]["overflowed"],
+           "overflowed": stats[-1]["overflowed"], "restarted": stats[-1]["restarted"],
+           "handoff_pool_words_asked": stats[-1]["handoff_words"],
            "box_checks_per_step": int(sum(sum(c) for c in stats[-1]["checks"])),
            "sequential_checks_per_step": int(seq),
            "promoted_per_step": stats[-1]["promoted"], "level_probes_per_step": stats[-1]["probes"],
@@ -494,6 +495,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per offered load of the serving measurement (0: skip)")
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9")
+    ap.add_argument("--budget-gib", type=int, default=160,
+                    help="scratch budget of the measuring context (at most 60%% of free HBM)")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-target-us", type=int, default=5000,
                     help="server's launch latency target (0: launches bounded by size only)")
@@ -533,7 +536,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ctx = ccd.Context(0, mem_budget_bytes=32 << 30)
+    # scratch budget: most of the 288 GB of HBM, so that the group -> block
+    # hand-off pool holds every hand-off of the heaviest query sets (a
+    # hand-off the pool cannot take restarts its query at level 0)
+    free_bytes, _ = torch.cuda.mem_get_info(dev)
+    budget = min(args.budget_gib << 30, int(free_bytes * 0.6))
+    ctx = ccd.Context(0, mem_budget_bytes=budget)
     key = f"{w['name']}_delta{w['delta']:g}"
     autotune = apply_tuning(ctx, args, key, w, pos, kind)
     tuning = ctx.tuning()
@@ -618,6 +626,8 @@ def main():
         "promoted_per_step": stats_p[-1]["promoted"],
         "level_probes_per_step": stats_p[-1]["probes"],
         "overflowed_per_step": stats_p[-1]["overflowed"],
+        "restarted_per_step": stats_p[-1]["restarted"],
+        "scratch_budget_bytes": budget,
         "lane_utilization": [round(sum(stats_p[-1]["checks"][i]) / stats_p[-1]["lane_slots"][i], 3)
                              if stats_p[-1]["lane_slots"][i] else None for i in range(3)],
         "roofline": rl,

@@ -159,10 +159,13 @@ typedef struct ccd_tuning {
                                      enough for every query, clamped to a quarter of the
                                      budget.  Never below group_capacity.  A query whose
                                      level outgrows it returns with CCD_ST_OVERFLOW. */
-    int64_t handoff_words;        /* pool (8-byte words) carrying a wide query's current level
-                                     from the group to the block engine; when it is full
-                                     the block engine restarts such a query at level 0
-                                     (same results, more work).  Default 2^25. */
+    int64_t handoff_words;        /* largest pool (8-byte words) carrying a wide query's
+                                     current level from the group to the block engine; the
+                                     pool gets up to an eighth of the budget left after one
+                                     arena of each engine, and after the engines' arenas
+                                     whatever the budget still leaves.  When it is full the
+                                     block engine restarts such a query at level 0 (same
+                                     results, more work).  Default 2^33. */
     int32_t group_lds_words;      /* the first words of each level of a wide query stay in LDS
                                      (two buffers per group; the rest of a level spills to
                                      the HBM arena), for one-wave groups at occupancy 3 and

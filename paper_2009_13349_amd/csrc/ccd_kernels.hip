@@ -1035,7 +1035,9 @@ struct GroupShared {
     unsigned long long next_box;  // W > 1: boxes of the next level
     int64_t rec;
     int64_t ho[2];      // hand-off: record index and pool offset (or -1)
-    uint64_t cand[64 * W];  // head try / level probe: unchecked words below the first colliding key
+    // head try / level probe: unchecked words below the first colliding key
+    // (multi-wave groups: two chunks, for the streamed candidate check)
+    uint64_t cand[W > 1 ? 128 * W : 64];
     unsigned int ncand; // cap-level probe: candidates gathered
 };
 
@@ -1429,20 +1431,60 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
             __syncthreads();
             const unsigned int ncand = uni32(sh.ncand);
             block_sum3(rmin, rmax, nprobe);
-            if (ncand <= (unsigned int)T) {
-                // the candidates (one chunk's worth, one per thread)
-                const bool cact = tid < (int)ncand;
-                const uint64_t cw = cact ? sh.cand[tid] : 0;
-                LaneBoxes C;
-                expand(cact, cw, 0, 0, C);
-                check(C);
+            // the candidates are checked one chunk's worth (T words) at a time:
+            // at most T of them are in sh.cand already; more (up to a quarter
+            // of the level's words, beyond which the full pass is cheaper) are
+            // gathered again from the level in storage order, the gathering
+            // stopping whenever a chunk's worth waits (sh.cand holds 2 T)
+            const bool stream = ncand > (unsigned int)T;
+            if (!stream || 4 * (uint64_t)ncand <= (uint64_t)words) {
                 KeyAcc G;
                 keyacc_init(G);
+                unsigned long long ncheck = 0;
+                int64_t sc = 0;  // streamed gathering: next storage chunk
+                if (stream) {
+                    __syncthreads();
+                    if (tid == 0) sh.ncand = 0;
+                    __syncthreads();
+                }
+                while (true) {
+                    unsigned int n = ncand;
+                    if (stream) {
+                        while (sc < words) {
+                            const int64_t j = sc + tid;
+                            if (j < words && !(j < cend || j >= c1)) {
+                                const uint64_t wd = ct.get(j);
+                                const uint64_t k0 = kPair ? pair_child(wd, psx, plowx, 0) : wd;
+                                if (k0 < gmin) sh.cand[atomicAdd(&sh.ncand, 1u)] = wd;
+                            }
+                            sc += T;
+                            __syncthreads();
+                            const unsigned int waiting = uni32(sh.ncand);
+                            __syncthreads();  // every wave has read it before the next appends
+                            if (waiting >= (unsigned int)T) break;
+                        }
+                        n = min(uni32(sh.ncand), (unsigned int)T);
+                    }
+                    if (n == 0) break;
+                    const bool cact = tid < (int)n;
+                    const uint64_t cw = cact ? sh.cand[tid] : 0;
+                    LaneBoxes C;
+                    expand(cact, cw, 0, 0, C);
+                    check(C);
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    if (C.R[b].collide)
-                        keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small, false, -1);
-                unsigned long long ncheck = (C.act[0] ? 1 : 0) + (C.act[1] ? 1 : 0);
+                    for (int b = 0; b < 2; ++b)
+                        if (C.R[b].collide)
+                            keyacc_add(G, C.key[b], C.it[b], C.R[b].small || L.dcap, C.R[b].small, false, -1);
+                    ncheck += (C.act[0] ? 1 : 0) + (C.act[1] ? 1 : 0);
+                    if (!stream) break;
+                    // the waiting words beyond the checked chunk move to the front
+                    const unsigned int m = uni32(sh.ncand);
+                    const uint64_t rest = (unsigned int)tid + T < m ? sh.cand[T + tid] : 0;
+                    __syncthreads();
+                    if ((unsigned int)tid + T < m) sh.cand[tid] = rest;
+                    if (tid == 0) sh.ncand = m > (unsigned int)T ? m - T : 0;
+                    __syncthreads();
+                }
                 block_keyacc(G);
                 uint64_t f = gmin;
                 uint32_t ff = P.ff;

@@ -120,7 +120,7 @@ void default_tuning(ccd_tuning& t, int num_cu) {
     t.block_count = num_cu;
     t.group_occupancy = 3;
     t.block_capacity = 0;             // 2 m_I + 2, within the budget
-    t.handoff_words = int64_t(1) << 25;  // 256 MiB
+    t.handoff_words = int64_t(1) << 33;  // 64 GiB: in practice what the budget leaves
     t.group_lds_words = 0;            // off: measured slower on the simulation-shaped workload
     t.block_lds_words = 2048;         // 32 KiB per eight-wave block
 }
@@ -244,16 +244,21 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
     // one arena of each engine always (per_block <= left / 4, or = per_group
     // <= left / 2: both fit)
     left -= per_group + per_block;
-    // hand-off pool: the tuning's size, at most an eighth of what is left
+    // hand-off pool, first share: the tuning's size, at most an eighth of what
+    // is left
     P.pool_words = std::min<int64_t>(t.handoff_words, (int64_t)(left / 8 / 8));
     left -= (size_t)P.pool_words * 8;
     // the group engine carries the bulk of the work: further groups get up to
-    // 3/4 of what is left; further blocks (rarely used) the rest
+    // 3/4 of what is left; further blocks the rest
     const size_t more_groups = (left / 4 * 3) / per_group;
     P.group_count = (int)std::min<size_t>((size_t)std::max(P.group_count, 1), 1 + more_groups);
     left -= (size_t)(P.group_count - 1) * per_group;
     const size_t blocks_fit = 1 + left / per_block;
     P.block_count = (int)std::min<size_t>((size_t)P.block_count, blocks_fit);
+    left -= (size_t)(P.block_count - 1) * per_block;
+    // the pool takes what remains, up to the tuning's size: every hand-off
+    // beyond it restarts its query at level 0 (the same result, more work)
+    P.pool_words += std::min<int64_t>(t.handoff_words - P.pool_words, (int64_t)(left / 8));
     return CCD_OK;
 }
 
