@@ -121,6 +121,15 @@ def test_scratch_plan_sizes_are_overflow_safe(lib):
                 assert e.code == ccd.ENOMEM
                 continue
             assert p["bytes"] <= b, (b, n, p)
+    # the hand-off pool takes what the engines' arenas leave, up to handoff_words
+    big = ccd.plan_scratch(1_000_000, 10 ** 6, mem_budget_bytes=160 << 30)
+    assert big["handoff_words"] == 1 << 33 and big["group_count"] == 3072 and big["block_count"] == 256
+    for b in (16 << 30, 32 << 30):
+        p = ccd.plan_scratch(1_000_000, 10 ** 6, mem_budget_bytes=b)
+        assert b - 8 * 48 * max(p["group_capacity"], p["block_capacity"]) < p["bytes"] <= b
+        assert p["handoff_words"] * 8 >= b // 16
+    capped = ccd.plan_scratch(1_000_000, 10 ** 6, mem_budget_bytes=160 << 30, handoff_words=1 << 20)
+    assert capped["handoff_words"] == 1 << 20 and capped["bytes"] < big["bytes"]
     # a tuning can shrink the block arena (never below a group arena)
     p = ccd.plan_scratch(1000, 10 ** 6, mem_budget_bytes=budget, group_capacity=256,
                          block_capacity=300)
