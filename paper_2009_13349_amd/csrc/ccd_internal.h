@@ -21,6 +21,7 @@ enum Counter : int {
     kCntDeep,            // lane engine: queries handed on because a level passed depth sum 64
     kCntProbe,           // group engines: level probes run
     kCntProbeHit,        // group engines: level probes that decided the level
+    kCntTail,            // single-wave groups: levels handed on after their queue drained
     kCntEnd,
 };
 static_assert(kCntEnd <= 64, "counters are cleared by one wavefront");
@@ -129,6 +130,9 @@ struct GroupCfg {
     int64_t out_pool_words;
     int32_t out_count_idx;
     int32_t tier;              // 1 (group) or 2 (block), for the check counters
+    int64_t tail_records;      // single-wave groups whose input records are all taken hand
+                               // on a level of capacity / 16 words or more, at most this
+                               // many times per launch (0: never)
 };
 
 }  // namespace ccd

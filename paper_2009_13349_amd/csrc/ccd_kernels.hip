@@ -1971,19 +1971,22 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
         // word of this one), or this is a level where m_I can stop the query and
         // it spans more than a few chunks (the next engine's level probe
         // decides such a level without checking it in full), or (single-wave
-        // groups) every record of this engine has been taken and the level
-        // has at least cap / 16 words: the heavy queries that started last
+        // groups) every record of this engine has been taken, the level has
+        // at least cap / 16 words and fewer than g.tail_records such
+        // hand-offs have been made: the heavy queries that started last
         // would otherwise run their widest levels on one wave each while the
         // other groups sit idle, and the block engine checks them eight
         // waves at a time.  Hand the query on before checking this level, so
         // that the next engine checks it once.
         bool tail = false;
-        if (W == 1 && g.out_records && 16 * words >= cap) {
+        if (W == 1 && g.out_records && 16 * words >= cap &&
+            (int64_t)__atomic_load_n(&a.counters[kCntTail], __ATOMIC_RELAXED) < g.tail_records) {
             int64_t cnt = (int64_t)__atomic_load_n(&a.counters[g.in_count_idx], __ATOMIC_RELAXED);
             if (cnt > g.in_record_cap) cnt = g.in_record_cap;
             tail = (int64_t)__atomic_load_n(&a.counters[g.in_take_idx], __ATOMIC_RELAXED) >= cnt;
-            tail = uni32(tail ? 1u : 0u) != 0;
         }
+        tail = uni32(tail ? 1u : 0u) != 0;
+        if (tail && tid == 0) atomicAdd(&a.counters[kCntTail], 1ull);
         if (g.out_records && (2 * words > cap || (cap_level && words > 4 * T) || tail) &&
             handoff<W>(a, g, sh, S, fmt, pa, words, ct, cap, h.q))
             return;

@@ -376,6 +376,8 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     g.out_pool_words = P.pool_words;
     g.out_count_idx = kCntRecB;
     g.tier = 1;
+    // about two such hand-offs per block engine: more would queue there
+    g.tail_records = 2 * (int64_t)P.block_count;
     {
         const void* fn;
         int threads = 64;
@@ -425,6 +427,7 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     b.out_pool_words = 0;
     b.out_count_idx = 0;
     b.tier = 2;
+    b.tail_records = 0;
     if (tune.block_lds_words > 0) {
         b.lds_words = std::min<int64_t>(
             group_lds_words((const void*)&k_group<8, 1, true>, tune.block_lds_words, lds_per_block),
