@@ -206,10 +206,20 @@ def roofline(stats, min_sep: float = 0.0):
     }
 
 
-def kernel_symbol(tier: int, tuning: dict) -> str:
+BUDGET = [0]  # the measuring context's scratch budget (bytes)
+
+
+def kernel_symbol(tier: int, tuning: dict, n: int = 1_000_000, max_iter: int = 1_000_000,
+                  num_cu: int = 256) -> str:
+    """The kernel a tier runs (the block tier: four-wave engines when the
+    scratch plan has at least two block engines per CU)."""
     if tier == 0:
         return "ccd::k_lane<true>"
     if tier == 2:
+        from paper_2009_13349_amd import ccd
+        plan = ccd.plan_scratch(n, max_iter, num_cu, mem_budget_bytes=BUDGET[0], **tuning)
+        if plan["block_count"] >= 2 * num_cu:
+            return "ccd::k_group<4, 1, false>"
         return f"ccd::k_group<8, 1, {'true' if tuning['block_lds_words'] > 0 else 'false'}>"
     gw = tuning["group_waves"]
     occ = tuning["group_occupancy"] if gw == 1 else 1
@@ -301,7 +311,7 @@ def measure_workload(ctx, torch, w, steps, warmup):
     seq = float(out.n_checks.to(torch.float64).sum().item())
     rl = roofline(stats, w["min_sep"])
     tier = KERNELS.index(rl["kernel"]) - 1
-    rl["symbol"] = kernel_symbol(tier, ctx.tuning())
+    rl["symbol"] = kernel_symbol(tier, ctx.tuning(), n, w["max_iter"])
     res = {"queries": n, "value": round(n * steps / t, 1), "ms_per_step": round(1e3 * t / steps, 3),
            "steps": steps, "delta": w["delta"], "max_iter": w["max_iter"], "min_sep": w["min_sep"],
            "hits": int(out.hit.sum().item()),
@@ -319,12 +329,18 @@ def measure_workload(ctx, torch, w, steps, warmup):
 
 def measure_configs(ctx, torch, steps):
     """The other query sets of the benchmark, each with the main workload's
-    tuning: 4,096 uniform vertex-face queries; 100,000 edge-edge queries with
-    10% degenerate cases (their parallel and coplanar pairs run to the m_I cap);
+    tuning but the library's default block engines (two four-wave engines per
+    CU: these sets send thousands of capped queries to the block tier, where
+    more engines at once beat eight waves per query; the main workload sends
+    it a few hundred levels and keeps one eight-wave engine per CU):
+    4,096 uniform vertex-face queries; 100,000 edge-edge queries with 10%
+    degenerate cases (their parallel and coplanar pairs run to the m_I cap);
     1,000,000 minimum-separation queries at d in {1e-4, 1e-3} x delta in
     {1e-6, 1e-4}."""
     from paper_2009_13349_amd import workloads as W
-    out = {}
+    num_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    ctx.set_tuning(block_count=2 * num_cu)
+    out = {"tuning": ctx.tuning()}
     w = W.uniform_vf(4096, seed=0)
     out[w["name"]] = measure_workload(ctx, torch, w, max(steps, 20), 3)
     w = W.edge_edge_mixed(100_000, seed=1)
@@ -541,6 +557,7 @@ def main():
     # hand-off the pool cannot take restarts its query at level 0)
     free_bytes, _ = torch.cuda.mem_get_info(dev)
     budget = min(args.budget_gib << 30, int(free_bytes * 0.6))
+    BUDGET[0] = budget
     ctx = ccd.Context(0, mem_budget_bytes=budget)
     key = f"{w['name']}_delta{w['delta']:g}"
     autotune = apply_tuning(ctx, args, key, w, pos, kind)
@@ -576,7 +593,7 @@ def main():
         ctx.set_tuning(**tuning)
     rl = roofline(stats_p)
     tier = KERNELS.index(rl["kernel"]) - 1
-    rl["symbol"] = kernel_symbol(tier, tuning)
+    rl["symbol"] = kernel_symbol(tier, tuning, n, w["max_iter"])
     tk, same = profile_record("hbm_traffic.json", rl["symbol"], tuning)
     tb = tk["fetch_bytes"] + tk["write_bytes"] if tk and tk.get("fetch_bytes") is not None else None
     rl["traffic"] = round(tb) if tb else None

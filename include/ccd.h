@@ -152,7 +152,9 @@ typedef struct ccd_tuning {
     int32_t group_waves;          /* waves per group working on one wide query (1, 2, 4, 8) */
     int32_t group_count;          /* resident groups of the wide-query kernel */
     int64_t group_capacity;       /* boxes per level of a group's arena */
-    int32_t block_count;          /* resident blocks of the huge-query kernel */
+    int32_t block_count;          /* engines of the huge-query kernel (default 2 per CU); with
+                                     at least 2 per CU each is a workgroup of 4 waves, else
+                                     of 8 waves (the budget can lower the count) */
     int32_t group_occupancy;      /* single-wave groups: minimum waves per SIMD the register
                                      allocation must allow (1..4) */
     int64_t block_capacity;       /* words per level of a huge-query arena; 0 (default): 2 m_I + 2,

@@ -117,7 +117,7 @@ void default_tuning(ccd_tuning& t, int num_cu) {
     t.group_waves = 1;
     t.group_count = num_cu * 12;
     t.group_capacity = 1 << 16;
-    t.block_count = num_cu;
+    t.block_count = 2 * num_cu;
     t.group_occupancy = 3;
     t.block_capacity = 0;             // 2 m_I + 2, within the budget
     t.handoff_words = int64_t(1) << 33;  // 64 GiB: in practice what the budget leaves
@@ -178,6 +178,7 @@ struct Plan {
     int64_t group_cap;
     int block_count;
     int64_t block_cap;
+    int block_waves;     // 4 when there are at least two block engines per CU, else 8
 };
 
 // Saturating size arithmetic: a result that does not fit size_t becomes
@@ -256,6 +257,10 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
     const size_t blocks_fit = 1 + left / per_block;
     P.block_count = (int)std::min<size_t>((size_t)P.block_count, blocks_fit);
     left -= (size_t)(P.block_count - 1) * per_block;
+    // two four-wave engines per CU check more wide queries at once than one
+    // eight-wave engine (each keeps two waves per SIMD at its register use);
+    // with fewer engines than that, each gets eight waves
+    P.block_waves = P.block_count >= 2 * num_cu ? 4 : 8;
     // the pool takes what remains, up to the tuning's size: every hand-off
     // beyond it restarts its query at level 0 (the same result, more work)
     P.pool_words += std::min<int64_t>(t.handoff_words - P.pool_words, (int64_t)(left / 8));
@@ -428,7 +433,10 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     b.out_count_idx = 0;
     b.tier = 2;
     b.tail_records = 0;
-    if (tune.block_lds_words > 0) {
+    if (P.block_waves == 4) {
+        b.lds_words = 0;
+        hipLaunchKernelGGL((k_group<4, 1, false>), dim3(P.block_count), dim3(256), 0, s, a, b);
+    } else if (tune.block_lds_words > 0) {
         b.lds_words = std::min<int64_t>(
             group_lds_words((const void*)&k_group<8, 1, true>, tune.block_lds_words, lds_per_block),
             P.block_cap);

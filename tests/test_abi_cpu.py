@@ -123,7 +123,7 @@ def test_scratch_plan_sizes_are_overflow_safe(lib):
             assert p["bytes"] <= b, (b, n, p)
     # the hand-off pool takes what the engines' arenas leave, up to handoff_words
     big = ccd.plan_scratch(1_000_000, 10 ** 6, mem_budget_bytes=160 << 30)
-    assert big["handoff_words"] == 1 << 33 and big["group_count"] == 3072 and big["block_count"] == 256
+    assert big["handoff_words"] == 1 << 33 and big["group_count"] == 3072 and big["block_count"] == 512
     for b in (16 << 30, 32 << 30):
         p = ccd.plan_scratch(1_000_000, 10 ** 6, mem_budget_bytes=b)
         assert b - 8 * 48 * max(p["group_capacity"], p["block_capacity"]) < p["bytes"] <= b

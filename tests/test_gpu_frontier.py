@@ -58,6 +58,18 @@ def test_group_to_block_continues_at_the_level(ctx, torch_dev, wide):
     assert block_cont < block_restart, (block_cont, block_restart)
 
 
+def test_four_wave_block_engines(ctx, torch_dev, wide):
+    """Two block engines per CU (small block arenas so that they fit the
+    budget) run as four-wave workgroups; same results."""
+    w, ref = wide
+    ctx.set_tuning(lane_capacity=8, lane_budget=1, group_capacity=256, block_capacity=65536,
+                   block_count=2 * torch_dev[0].cuda.get_device_properties(0).multi_processor_count)
+    got = run_gpu(ctx, torch_dev, w, 0)
+    st = ctx.last_stats()
+    assert_same(got, ref, what="four-wave block engines")
+    assert st["promoted"][1] > 0 and st["restarted"] == 0 and st["overflowed"] == 0
+
+
 def test_drained_group_queue_hands_wide_levels_on(ctx, torch_dev, wide):
     """Every record of the group engine is taken at once (fewer queries than
     groups): a level of at least cap / 16 words goes to the block engine
