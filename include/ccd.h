@@ -256,7 +256,7 @@ int ccd_batch(ccd_context* ctx, const ccd_batch_desc* desc, const ccd_result_soa
  * 256 MiB per GPU, loaded with the library and held until the process ends.
  * A batch whose scratch plan (ccd_plan_scratch with a 256 MiB budget) does
  * not fit is rejected with CCD_ENOMEM before anything is launched; with the
- * default tuning that is a batch of more than about 900,000 queries.  With
+ * default tuning that is a batch of more than about 960,000 queries.  With
  * per-query m_I (max_iter_q) the block engine's arena takes what the array
  * allows and a query needing more returns with CCD_ST_OVERFLOW.
  * Every call on a GPU shares that GPU's array, which keeps the last call's
