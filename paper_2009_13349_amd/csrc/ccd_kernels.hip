@@ -985,8 +985,9 @@ __device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
     const uint32_t ff = uni32((uint32_t)__shfl((int)K.ff, l));
     const int64_t fpos = uni64s(__shfl(K.fpos, l));
     const uint64_t mh = __ballot(K.mh != 0), th = __ballot(K.th != 0);
-    const uint64_t m = wave_max_u64(K.mh ? K.m : 0ull);
-    const uint64_t tm = wave_min_u64(K.th ? K.tm : ~0ull);
+    // (most levels have neither: no m_I stop possible, no terminal box)
+    const uint64_t m = mh ? wave_max_u64(K.mh ? K.m : 0ull) : 0ull;
+    const uint64_t tm = th ? wave_min_u64(K.th ? K.tm : ~0ull) : ~0ull;
     K.f = hold ? g : ~0ull;
     K.ff = hold ? ff : 0u;
     K.fpos = hold ? fpos : -1;
@@ -2022,8 +2023,9 @@ __device__ __forceinline__ void group_query(const BatchArgs& a, const GroupCfg& 
         // f is colliding and not terminal here, so its word (pairs) or child 0
         // (triples) is on the next level and holds that level's smallest key
         // (bisection preserves Alg. 2's order): store it first, where the head
-        // try looks first
-        if (A.fpos > 0) {
+        // try and the level probe look first (a level of one chunk is checked
+        // whole in its first chunk anyway)
+        if (A.fpos > 0 && nw > (uint64_t)T) {
             __syncthreads();
             if (tid == 0) {
                 const int64_t p = A.fpos;
