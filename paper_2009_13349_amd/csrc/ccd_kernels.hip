@@ -954,6 +954,13 @@ __device__ __forceinline__ void keyacc_merge(KeyAcc& K, const KeyAcc& B) {
     if (B.th && (!K.th || B.tm < K.tm)) { K.tm = B.tm; K.th = 1; }
 }
 
+// Lane l's value (l wave-uniform): two v_readlane, no LDS round trip.
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -982,8 +989,8 @@ __device__ __forceinline__ void keyacc_reduce(KeyAcc& K) {
     const uint64_t g = wave_min_u64(hf ? K.f : ~0ull);
     const uint64_t hold = __ballot(hf && K.f == g);
     const int l = hold ? __builtin_ctzll(hold) : 0;
-    const uint32_t ff = uni32((uint32_t)__shfl((int)K.ff, l));
-    const int64_t fpos = uni64s(__shfl(K.fpos, l));
+    const uint32_t ff = (uint32_t)__builtin_amdgcn_readlane((int)K.ff, l);
+    const int64_t fpos = (int64_t)readlane64((uint64_t)K.fpos, l);
     const uint64_t mh = __ballot(K.mh != 0), th = __ballot(K.th != 0);
     // (most levels have neither: no m_I stop possible, no terminal box)
     const uint64_t m = mh ? wave_max_u64(K.mh ? K.m : 0ull) : 0ull;
@@ -1579,7 +1586,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
                 t = atomicAdd(&sh.next_cnt, wtot);
                 atomicAdd(&sh.next_box, btot);
             }
-            wbase = uni64(__shfl(t, 0));
+            wbase = readlane64(t, 0);
         }
         if (OP) {
             // one word per stored box; mk[2], mk[3] only count boxes
