@@ -961,23 +961,39 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t y = __shfl_xor(x, off);
-        x = y < x ? y : x;
-    }
-    return uni64(x);
+// Wavefront minimum / maximum of a 64-bit value with DPP moves (no LDS round
+// trips): within each row of 16 lanes a running prefix (row_shr 1, 2, 3, then
+// 4 and 8 on the upper banks) leaves the row's result in its lane 15; the
+// row broadcasts (lane 15 into rows 1 and 3, then lane 31 into rows 2 and 3)
+// fold the rows, so that lane 63 holds the wave's result.  A lane whose DPP
+// source is masked or outside its row receives the identity.
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x, uint64_t ident) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)ident, (int)(uint32_t)x,
+                                                              CTRL, ROWS, BANKS, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(ident >> 32),
+                                                              (int)(uint32_t)(x >> 32), CTRL, ROWS,
+                                                              BANKS, false);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t y = __shfl_xor(x, off);
-        x = y > x ? y : x;
-    }
-    return uni64(x);
+template <bool MAX>
+__device__ __forceinline__ uint64_t wave_ext_u64(uint64_t x) {
+    const uint64_t id = MAX ? 0ull : ~0ull;
+    auto pick = [](uint64_t a, uint64_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    const uint64_t x0 = x;
+    x = pick(x, dpp_u64<0x111, 0xf, 0xf>(x0, id));  // row_shr:1
+    x = pick(x, dpp_u64<0x112, 0xf, 0xf>(x0, id));  // row_shr:2
+    x = pick(x, dpp_u64<0x113, 0xf, 0xf>(x0, id));  // row_shr:3
+    x = pick(x, dpp_u64<0x114, 0xf, 0xe>(x, id));   // row_shr:4, banks 1-3
+    x = pick(x, dpp_u64<0x118, 0xf, 0xc>(x, id));   // row_shr:8, banks 2-3
+    x = pick(x, dpp_u64<0x142, 0xa, 0xf>(x, id));   // row_bcast:15, rows 1 and 3
+    x = pick(x, dpp_u64<0x143, 0xc, 0xf>(x, id));   // row_bcast:31, rows 2 and 3
+    return readlane64(x, 63);
 }
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) { return wave_ext_u64<false>(x); }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) { return wave_ext_u64<true>(x); }
 
 // Wavefront reduction; the result is made wave-uniform.  Keys of one level are
 // distinct, so the smallest one is held by exactly one lane, which supplies its
