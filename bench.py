@@ -328,28 +328,45 @@ def measure_workload(ctx, torch, w, steps, warmup):
 
 
 def measure_configs(ctx, torch, steps):
-    """The other query sets of the benchmark, each with the main workload's
-    tuning but the library's default block engines (two four-wave engines per
-    CU: these sets send thousands of capped queries to the block tier, where
-    more engines at once beat eight waves per query; the main workload sends
-    it a few hundred levels and keeps one eight-wave engine per CU):
-    4,096 uniform vertex-face queries; 100,000 edge-edge queries with 10%
-    degenerate cases (their parallel and coplanar pairs run to the m_I cap);
-    1,000,000 minimum-separation queries at d in {1e-4, 1e-3} x delta in
-    {1e-6, 1e-4}."""
+    """The other query sets of the benchmark, each with its own entry of the
+    committed MI355X tuning file when it has one (autotuner results, searched
+    from the main workload's tuning with two block engines per CU), else the
+    main workload's tuning with the library's default block engines (two
+    four-wave engines per CU: these sets send thousands of capped queries to
+    the block tier, where more engines at once beat eight waves per query;
+    the main workload sends it a few hundred levels and keeps one eight-wave
+    engine per CU): 4,096 uniform vertex-face queries; 100,000 edge-edge
+    queries with 10% degenerate cases (their parallel and coplanar pairs run
+    to the m_I cap); 1,000,000 minimum-separation queries at d in
+    {1e-4, 1e-3} x delta in {1e-6, 1e-4}."""
     from paper_2009_13349_amd import workloads as W
     num_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    ctx.set_tuning(block_count=2 * num_cu)
-    out = {"tuning": ctx.tuning()}
+    main = ctx.tuning()
+    fallback = dict(main, block_count=2 * num_cu)
+    out = {}
+
+    def measure(w, steps_w, warm):
+        key = f"{w['name']}_delta{w['delta']:g}"
+        if ctx.tuning_cache_load(COMMITTED_TUNING, key):
+            src = "committed tuning file (autotuner result on MI355X)"
+        else:
+            ctx.set_tuning(**fallback)
+            src = "main workload's tuning, default block engines"
+        res = measure_workload(ctx, torch, w, steps_w, warm)
+        res["tuning_source"] = src
+        res["tuning"] = ctx.tuning()
+        return res
+
     w = W.uniform_vf(4096, seed=0)
-    out[w["name"]] = measure_workload(ctx, torch, w, max(steps, 20), 3)
+    out[w["name"]] = measure(w, max(steps, 20), 3)
     w = W.edge_edge_mixed(100_000, seed=1)
-    out[w["name"]] = measure_workload(ctx, torch, w, max(2, steps // 4), 1)
+    out[w["name"]] = measure(w, max(2, steps // 4), 1)
     for d in (1e-4, 1e-3):
         for delta in (1e-6, 1e-4):
             w = W.min_separation(1_000_000, seed=2, d_min=d, delta=delta)
-            out[w["name"]] = measure_workload(ctx, torch, w, 2, 1)
+            out[w["name"]] = measure(w, 2, 1)
             del w
+    ctx.set_tuning(**main)
     return out
 
 
