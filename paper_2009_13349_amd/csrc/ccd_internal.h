@@ -121,6 +121,7 @@ struct GroupCfg {
     int64_t in_record_words;
     int64_t in_record_cap;
     const uint64_t* in_pool;   // non-null: the input records' boxes are in this pool
+    const int64_t* in_perm;    // non-null: the order in which the input records are taken
     int32_t in_count_idx;      // counter holding the number of input records
     int32_t in_take_idx;       // counter used to take input records
     uint64_t* out_records;     // hand-off records for the next engine (or null: none)

@@ -607,6 +607,42 @@ __global__ void k_reset(unsigned long long* counters) {
     if (i < kCntEnd) counters[i] = 0;
 }
 
+// Orders the group engine's input records by the level at which the lane
+// engine handed their query on, lowest first: a query whose level outgrew the
+// lane frontier early branches widely and tends to need far more checks (on
+// the simulation-shaped workload the rank correlation of that level with the
+// query's check count is -0.85), and a single-wave group that takes such a
+// query last holds the launch open long after the other groups are done.
+// Any order gives the same results.  One workgroup: a counting sort over the
+// 64 possible levels; perm receives record indices.
+__global__ __launch_bounds__(1024) void k_order_records(const unsigned long long* counters,
+                                                        const uint64_t* rec, int64_t rec_words,
+                                                        int64_t cap, int32_t count_idx,
+                                                        int64_t* perm) {
+    __shared__ unsigned long long hist[64];
+    const int tid = threadIdx.x;
+    int64_t count = (int64_t)counters[count_idx];
+    if (count > cap) count = cap;
+    if (tid < 64) hist[tid] = 0;
+    __syncthreads();
+    auto level_of = [&](int64_t i) {
+        const int lv = reinterpret_cast<const Record*>(rec + i * rec_words)->level;
+        return lv < 0 ? 0 : (lv > 63 ? 63 : lv);
+    };
+    for (int64_t i = tid; i < count; i += 1024) atomicAdd(&hist[level_of(i)], 1ull);
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long run = 0;
+        for (int l = 0; l < 64; ++l) {
+            const unsigned long long c = hist[l];
+            hist[l] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < count; i += 1024) perm[atomicAdd(&hist[level_of(i)], 1ull)] = i;
+}
+
 // ---------------------------------------------------------------------------
 // Packed keys.  A level whose total bisection depth D = dt + du + dv is at
 // most 64 stores each box as one u64 key
@@ -2096,7 +2132,7 @@ __global__ __launch_bounds__(64 * W, OCC) void k_group(BatchArgs a, GroupCfg g) 
         __syncthreads();
         const int64_t r = uni64s(sh.rec);
         if (r >= in_count) break;
-        const uint64_t* rec = g.in_records + r * g.in_record_words;
+        const uint64_t* rec = g.in_records + (g.in_perm ? g.in_perm[r] : r) * g.in_record_words;
         // everything below is per query, hence wave-uniform (scalar registers)
         Record h = *reinterpret_cast<const Record*>(rec);
         h.q = uni64s(h.q);

@@ -36,6 +36,8 @@ __global__ void k_scene_gamma_init(unsigned long long* g);
 __global__ void k_scene_gamma(const double* v0, const double* v1, int64_t nv, unsigned long long* g);
 __global__ void k_min_toi(const double* toi, int64_t n, unsigned long long* out);
 __global__ void k_reset(unsigned long long* counters);
+__global__ void k_order_records(const unsigned long long* counters, const uint64_t* rec,
+                                int64_t rec_words, int64_t cap, int32_t count_idx, int64_t* perm);
 }  // namespace ccd
 
 using namespace ccd;
@@ -365,6 +367,10 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
         hipLaunchKernelGGL(k_lane<false>, dim3(P.lane_grid), dim3(kLaneBlock), P.lane_lds, s, a, lc);
     if (timed) (void)hipEventRecord(ev[2], s);
 
+    // the lane engine's records, heavy-looking queries first (the order
+    // buffer, n entries, is free once the lane engine has run)
+    hipLaunchKernelGGL(k_order_records, dim3(1), dim3(1024), 0, s, (const unsigned long long*)X.counters,
+                       (const uint64_t*)X.rec_a, P.rec_a_words, P.rec_a_cap, (int32_t)kCntRecA, X.order);
     GroupCfg g;
     g.capacity = P.group_cap;
     g.arena = X.group_arena;
@@ -372,6 +378,7 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     g.in_record_words = P.rec_a_words;
     g.in_record_cap = P.rec_a_cap;
     g.in_pool = nullptr;
+    g.in_perm = X.order;
     g.in_count_idx = kCntRecA;
     g.in_take_idx = kCntRecATake;
     g.out_records = X.rec_b;
@@ -423,6 +430,7 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     b.in_record_words = P.rec_b_words;
     b.in_record_cap = P.rec_b_cap;
     b.in_pool = X.pool;
+    b.in_perm = nullptr;
     b.in_count_idx = kCntRecB;
     b.in_take_idx = kCntRecBTake;
     b.out_records = nullptr;
