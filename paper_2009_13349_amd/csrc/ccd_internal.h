@@ -110,6 +110,7 @@ struct LaneCfg {
     uint64_t* records;         // promotion records, stride record_words
     int64_t record_words;
     int64_t record_cap;
+    uint8_t* record_levels;    // each record's level (at most 63), for ordering them
 };
 
 struct GroupCfg {

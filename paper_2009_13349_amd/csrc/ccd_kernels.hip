@@ -614,22 +614,18 @@ __global__ void k_reset(unsigned long long* counters) {
 // query's check count is -0.85), and a single-wave group that takes such a
 // query last holds the launch open long after the other groups are done.
 // Any order gives the same results.  One workgroup: a counting sort over the
-// 64 possible levels; perm receives record indices.
+// 64 possible levels (the lane engine writes each record's level to a byte
+// array beside the records); perm receives record indices.
 __global__ __launch_bounds__(1024) void k_order_records(const unsigned long long* counters,
-                                                        const uint64_t* rec, int64_t rec_words,
-                                                        int64_t cap, int32_t count_idx,
-                                                        int64_t* perm) {
+                                                        const uint8_t* levels, int64_t cap,
+                                                        int32_t count_idx, int64_t* perm) {
     __shared__ unsigned long long hist[64];
     const int tid = threadIdx.x;
     int64_t count = (int64_t)counters[count_idx];
     if (count > cap) count = cap;
     if (tid < 64) hist[tid] = 0;
     __syncthreads();
-    auto level_of = [&](int64_t i) {
-        const int lv = reinterpret_cast<const Record*>(rec + i * rec_words)->level;
-        return lv < 0 ? 0 : (lv > 63 ? 63 : lv);
-    };
-    for (int64_t i = tid; i < count; i += 1024) atomicAdd(&hist[level_of(i)], 1ull);
+    for (int64_t i = tid; i < count; i += 1024) atomicAdd(&hist[levels[i] & 63], 1ull);
     __syncthreads();
     if (tid == 0) {
         unsigned long long run = 0;
@@ -640,7 +636,7 @@ __global__ __launch_bounds__(1024) void k_order_records(const unsigned long long
         }
     }
     __syncthreads();
-    for (int64_t i = tid; i < count; i += 1024) perm[atomicAdd(&hist[level_of(i)], 1ull)] = i;
+    for (int64_t i = tid; i < count; i += 1024) perm[atomicAdd(&hist[levels[i] & 63], 1ull)] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -900,6 +896,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_lane(BatchArgs a, LaneCfg c) {
                 h.fmt = kFmtKey;
                 h.words = S.level == 0 ? 0 : S.cnt;
                 *reinterpret_cast<Record*>(rec) = h;
+                c.record_levels[r] = (uint8_t)(S.level < 63 ? S.level : 63);
                 uint64_t* boxes = rec + kRecordHeaderWords;
                 if (S.level != 0)
                     for (uint32_t i = 0; i < S.cnt; ++i) boxes[i] = slot(cur, i);

@@ -36,8 +36,8 @@ __global__ void k_scene_gamma_init(unsigned long long* g);
 __global__ void k_scene_gamma(const double* v0, const double* v1, int64_t nv, unsigned long long* g);
 __global__ void k_min_toi(const double* toi, int64_t n, unsigned long long* out);
 __global__ void k_reset(unsigned long long* counters);
-__global__ void k_order_records(const unsigned long long* counters, const uint64_t* rec,
-                                int64_t rec_words, int64_t cap, int32_t count_idx, int64_t* perm);
+__global__ void k_order_records(const unsigned long long* counters, const uint8_t* levels,
+                                int64_t cap, int32_t count_idx, int64_t* perm);
 }  // namespace ccd
 
 using namespace ccd;
@@ -223,7 +223,7 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
     P.group_count = t.group_count;
     P.block_count = t.block_count;
 
-    const size_t fixed = sadd(sadd(sadd(64 * 8, smul((size_t)n, 8)),                        // counters, order
+    const size_t fixed = sadd(sadd(sadd(64 * 8, smul((size_t)n, 9)),                        // counters, order + record levels
                                    smul(smul((size_t)P.rec_a_cap, (size_t)P.rec_a_words), 8)),  // records A
                               smul(smul((size_t)P.rec_b_cap, (size_t)P.rec_b_words), 8));       // records B
     const size_t per_group = smul((size_t)P.group_cap, kArenaBytesPerWord);
@@ -274,14 +274,14 @@ int make_plan(ccd_context* ctx, int64_t n, int64_t max_iter_max, bool persistent
 }
 
 size_t plan_bytes(const Plan& P) {
-    return 64 * 8 + (size_t)P.n * 8 + (size_t)P.rec_a_cap * P.rec_a_words * 8 +
+    return 64 * 8 + (size_t)P.n * 9 + (size_t)P.rec_a_cap * P.rec_a_words * 8 +
            (size_t)P.rec_b_cap * P.rec_b_words * 8 + (size_t)P.pool_words * 8 +
            (size_t)P.group_count * P.group_cap * kArenaBytesPerWord +
            (size_t)P.block_count * P.block_cap * kArenaBytesPerWord;
 }
 
 int ensure_scratch(ccd_context* ctx, const Plan& P) {
-    bool ok = grow(ctx->counters, 64 * 8) && grow(ctx->order, (size_t)P.n * 8) &&
+    bool ok = grow(ctx->counters, 64 * 8) && grow(ctx->order, (size_t)P.n * 9) &&
               grow(ctx->rec_a, (size_t)P.rec_a_cap * P.rec_a_words * 8) &&
               grow(ctx->rec_b, (size_t)P.rec_b_cap * P.rec_b_words * 8) &&
               grow(ctx->pool, (size_t)P.pool_words * 8) &&
@@ -361,6 +361,7 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     lc.records = X.rec_a;
     lc.record_words = P.rec_a_words;
     lc.record_cap = P.rec_a_cap;
+    lc.record_levels = (uint8_t*)(X.order + P.n);  // the order buffer's tail: n bytes
     if (persistent)
         hipLaunchKernelGGL(k_lane<true>, dim3(P.lane_grid), dim3(kLaneBlock), P.lane_lds, s, a, lc);
     else
@@ -370,7 +371,7 @@ void enqueue(const ccd_tuning& tune, const Plan& P, const Scratch& X, BatchArgs 
     // the lane engine's records, heavy-looking queries first (the order
     // buffer, n entries, is free once the lane engine has run)
     hipLaunchKernelGGL(k_order_records, dim3(1), dim3(1024), 0, s, (const unsigned long long*)X.counters,
-                       (const uint64_t*)X.rec_a, P.rec_a_words, P.rec_a_cap, (int32_t)kCntRecA, X.order);
+                       (const uint8_t*)(X.order + P.n), P.rec_a_cap, (int32_t)kCntRecA, X.order);
     GroupCfg g;
     g.capacity = P.group_cap;
     g.arena = X.group_arena;
@@ -951,7 +952,7 @@ bool carve(const Plan& P, void* base, size_t bytes, Scratch& X) {
         return (unsigned char*)base + o;
     };
     X.counters = (unsigned long long*)take(64 * 8);
-    X.order = (int64_t*)take((size_t)P.n * 8);
+    X.order = (int64_t*)take((size_t)P.n * 9);  // order, then one level byte per record
     X.rec_a = (uint64_t*)take(smul(smul((size_t)P.rec_a_cap, (size_t)P.rec_a_words), 8));
     X.rec_b = (uint64_t*)take(smul(smul((size_t)P.rec_b_cap, (size_t)P.rec_b_words), 8));
     X.pool = (uint64_t*)take(smul((size_t)P.pool_words, 8));
