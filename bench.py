@@ -370,16 +370,9 @@ def measure_configs(ctx, torch, steps):
     return out
 
 
-def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, load: float = 0.7,
-                  seed: int = 4, streams: int = 2, launch_target_us: int = 5000):
-    """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
-    log-uniform in [1e-6, 1e-4]) at `load` x the measured batch throughput,
-    submitted to the continuous-batching server; latency = scheduled arrival ->
-    results in the caller's arrays.  Request payloads are contiguous pinned
-    slices of the benchmark workload (a fixed set of `payloads` of them,
-    reused round robin)."""
-    from paper_2009_13349_amd import ccd
-    rng = np.random.default_rng(seed)
+def serve_payloads(w, torch, rng, payloads: int):
+    """Contiguous pinned slices of the benchmark workload, sizes log-uniform
+    in [1e3, 1e6]."""
     N = w["pos"].shape[1]
     sizes = np.round(np.exp(rng.uniform(math.log(1e3), math.log(1e6), size=payloads))).astype(int)
     pay = []
@@ -388,7 +381,46 @@ def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, loa
         pos = torch.from_numpy(np.ascontiguousarray(w["pos"][:, off:off + n])).pin_memory()
         kind = torch.from_numpy(np.ascontiguousarray(w["kind"][off:off + n])).pin_memory()
         pay.append((int(n), pos, kind))
-    mean_n = float(np.mean(sizes))
+    return pay, float(np.mean(sizes))
+
+
+def serve_saturation(w, torch, requests: int = 200, payloads: int = 64, seed: int = 4,
+                     streams: int = 2, launch_target_us: int = 5000):
+    """The serving path's own throughput: the same requests submitted back to
+    back (closed loop, everything queued at once), queries per second from
+    the first submission to the last result in host memory."""
+    from paper_2009_13349_amd import ccd
+    rng = np.random.default_rng(seed)
+    pay, _ = serve_payloads(w, torch, rng, payloads)
+    deltas = np.exp(rng.uniform(math.log(1e-6), math.log(1e-4), size=requests))
+    srv = ccd.Server(streams=streams, pool_bytes=16 << 30, scratch_bytes=12 << 30,
+                     max_queries_per_launch=4_000_000, launch_target_us=launch_target_us)
+    for n, pos, kind in pay[:4]:
+        srv.wait(srv.submit(pos, kind, delta=1e-6), 600_000)
+    t0 = time.monotonic()
+    tickets, qsum = [], 0
+    for i in range(requests):
+        n, pos, kind = pay[i % payloads]
+        tickets.append(srv.submit(pos, kind, delta=float(deltas[i])))
+        qsum += n
+    for t in tickets:
+        srv.wait(t, 600_000)
+    dt = time.monotonic() - t0
+    srv.close()
+    return qsum / dt
+
+
+def serve_latency(w, torch, q_sat: float, requests: int, payloads: int = 64, load: float = 0.7,
+                  seed: int = 4, streams: int = 2, launch_target_us: int = 5000):
+    """Poisson stream of requests (sizes log-uniform in [1e3, 1e6], delta
+    log-uniform in [1e-6, 1e-4]) at `load` x q_sat (the serving path's own
+    closed-loop throughput), submitted to the continuous-batching server;
+    latency = scheduled arrival -> results in the caller's arrays.  Request
+    payloads are contiguous pinned slices of the benchmark workload (a fixed
+    set of `payloads` of them, reused round robin)."""
+    from paper_2009_13349_amd import ccd
+    rng = np.random.default_rng(seed)
+    pay, mean_n = serve_payloads(w, torch, rng, payloads)
     lam = load * q_sat / mean_n  # requests per second
     gaps = rng.exponential(1.0 / lam, size=requests)
     deltas = np.exp(rng.uniform(math.log(1e-6), math.log(1e-4), size=requests))
@@ -673,8 +705,12 @@ def main():
     }
     loads = [float(x) for x in args.serve_loads.split(",") if x]
     if args.serve_requests > 0 and args.workload == "simulation" and not args.main_only:
-        runs = [serve_latency(w, torch, value, args.serve_requests, load=ld, streams=args.serve_streams,
+        sat = serve_saturation(w, torch, streams=args.serve_streams, launch_target_us=args.serve_target_us)
+        runs = [serve_latency(w, torch, sat, args.serve_requests, load=ld, streams=args.serve_streams,
                               launch_target_us=args.serve_target_us) for ld in loads]
+        for r in runs:
+            r["offered_load_of"] = "serving path's closed-loop throughput"
+            r["serving_saturation_queries_per_s"] = round(sat, 1)
         line["serve"] = min(runs, key=lambda r: abs(r["offered_load"] - 0.7))
         line["serve_loads"] = runs
     else:

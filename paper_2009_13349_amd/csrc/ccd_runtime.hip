@@ -264,8 +264,13 @@ int plan_for(const ccd_tuning& t, int num_cu, size_t budget, int64_t n, int64_t 
     // with fewer engines than that, each gets eight waves
     P.block_waves = P.block_count >= 2 * num_cu ? 4 : 8;
     // the pool takes what remains, up to the tuning's size: every hand-off
-    // beyond it restarts its query at level 0 (the same result, more work)
+    // beyond it restarts its query at level 0 (the same result, more work).
+    // Rounded down to 128 MiB steps, so that batches of other sizes (whose
+    // records take more or less of the budget) mostly plan the same pool and
+    // the context's grow-only buffer is not reallocated for a few bytes.
     P.pool_words += std::min<int64_t>(t.handoff_words - P.pool_words, (int64_t)(left / 8));
+    constexpr int64_t kPoolStep = int64_t(1) << 24;
+    if (P.pool_words > kPoolStep && P.pool_words < t.handoff_words) P.pool_words &= ~(kPoolStep - 1);
     return CCD_OK;
 }
 

@@ -478,6 +478,19 @@ int ccd_serve_open(const ccd_serve_config* cfg, ccd_server** out) {
             return rc;
         }
         ccd_context_enable_graphs(sl.ctx, 0);  // the request table changes every launch
+        // a fixed 1 GiB hand-off pool: sized by what the budget leaves, the
+        // pool would grow (a reallocation that stalls the device) whenever a
+        // launch smaller than any before it leaves more of the budget free
+        {
+            ccd_tuning t;
+            std::memset(&t, 0, sizeof(t));
+            t.handoff_words = int64_t(1) << 27;
+            rc = ccd_context_set_tuning(sl.ctx, &t);
+            if (rc != CCD_OK) {
+                destroy(s);
+                return rc;
+            }
+        }
         rc = reserve(sl.ctx, c.max_queries_per_launch, 1000000);
         if (rc != CCD_OK) {
             destroy(s);
