@@ -552,7 +552,15 @@ int reserve(ccd_context* ctx, int64_t n, int64_t mi_max) {
     Plan P;
     int rc = make_plan(ctx, n, std::max<int64_t>(mi_max, 1), ctx->engine == CCD_ENGINE_PERSISTENT, P);
     if (rc != CCD_OK) return rc;
-    return ensure_scratch(ctx, P);
+    rc = ensure_scratch(ctx, P);
+    if (rc != CCD_OK) return rc;
+    // a smaller batch leaves more of the budget to the engines and the pool:
+    // hold their sizes at this plan's, so that no later batch of up to n
+    // queries plans a larger buffer (reallocating it would stall the device)
+    ctx->tune.group_count = P.group_count;
+    ctx->tune.block_count = P.block_count;
+    ctx->tune.handoff_words = P.pool_words;
+    return CCD_OK;
 }
 
 bool host_valid(const double X[24], int kind, double delta, int64_t max_iter, double min_sep) {
