@@ -1103,7 +1103,7 @@ int ccd_autotune(ccd_context* ctx, const ccd_batch_desc* d, const ccd_result_soa
         {1, {32, 64, 128, 192, 256, 384, 512}},  // lane_budget
         {2, {8, 16, 32}},          // lane_capacity
         {3, {4, 8, 12}},           // lane_waves_per_cu
-        {4, {1, 2}},               // group_waves
+        {4, {1, 2, 4}},            // group_waves
         {5, {0, 256, 512}},        // group_lds_words
     };
     for (int pass = 0; pass < 2 && rc == CCD_OK; ++pass) {
