@@ -1304,6 +1304,7 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
     else acc_init(A);
     early = false;
     bool tried = !kHead;
+    const bool has_pend = !literal && S.tpend < INFINITY;  // a carried box exists
     uint64_t boxes_done = 0;
     unsigned long long next_w = 0, next_b = 0;  // W == 1: running sizes of the next level
     if (W > 1) {
@@ -1607,7 +1608,9 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
             e[b] = col[b] && !term[b];
             // vertex-face prism test of child 1; on a t split its (u_lo, v_lo) is
             // the box's own, which passed when the box was made
-            adm[b] = KIND != kVF || (B.u0[b] + du1) + (B.v0[b] + dv1) <= 1.0;
+            // (every box of a level has u_lo + v_lo <= 1, so child 1 of a t
+            // split is admitted without the test)
+            adm[b] = KIND != kVF || axis == 0 || (B.u0[b] + du1) + (B.v0[b] + dv1) <= 1.0;
         }
         // positions of what this lane stores for the next level
         int64_t q[2];
@@ -1708,9 +1711,12 @@ __device__ __forceinline__ void level_pass(GroupShared<W>& sh, const Buf& ct, co
         if (kHead && !tried) {
             bool ends = false;
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                ends = ends || (col[b] && (term[b] || cap_level ||
-                                           (!literal && S.tpend <= L.tmax * B.t0[b])));
+            for (int b = 0; b < 2; ++b) ends = ends || (col[b] && (term[b] || cap_level));
+            // the carried box can come first only when there is one
+            if (has_pend) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) ends = ends || (col[b] && S.tpend <= L.tmax * B.t0[b]);
+            }
             found = __ballot(ends) != 0;
         }
         return found;
